@@ -1,0 +1,140 @@
+/*
+ * xeng.h - C ABI of the MI355X X-engine.
+ *
+ * The X-engine of an FX correlator (paper Sec. 2 and Sec. 2.2): the voltages
+ * of every input have already been channelised by the F stage and transposed
+ * so that the samples of one frequency from all inputs sit together (the
+ * "corner turn", Sec. 2.1).  For every frequency channel f the engine forms
+ * the complex multiply-accumulate of every pair of inputs, auto-correlations
+ * included, and integrates it over a chosen duration:
+ *
+ *     V[f][k(i,j)] = sum_t x_i(t,f) * conj(x_j(t,f)),   0 <= j <= i < N,
+ *     k(i,j) = i(i+1)/2 + j     ("fix one input, run over all inputs up to and
+ *                                 including itself", Sec. 2.3)
+ *
+ * Input samples (Sec. 2.1 equaliser, Sec. 2.3 packet payload): one byte per
+ * complex sample, real part = 4-bit two's complement in bits 7..4, imaginary
+ * part = 4-bit two's complement in bits 3..0 (code 1000b decodes as -8).
+ * Voltage blocks are uint8 [T][F][N] (time, channel, input), input fastest.
+ *
+ * Output: int32 [F][N(N+1)/2][2], (re, im) interleaved, channel-major, in the
+ * k(i,j) order above; V_ji = conj(V_ij) gives the upper triangle.  Values are
+ * the exact integer sums (no averaging; divide by n_integrated for a mean).
+ *
+ * All entry points return an xeng status (0 = OK, < 0 = error) unless stated;
+ * no entry point throws or aborts.  Device pointers are HIP device memory of
+ * the device current when the plan was made.  Every call on one plan must come
+ * from one host thread at a time.
+ */
+#ifndef XENG_H
+#define XENG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xeng_plan_s xeng_plan_t;
+
+/* One independent array: N inputs, F channels, and the largest number of
+ * time samples one xeng_correlate call may pass for it. */
+typedef struct {
+    int32_t n_inputs;           /* N, 1 .. XENG_MAX_INPUTS              */
+    int32_t n_chans;            /* F, >= 1                              */
+    int64_t max_time_per_call;  /* >= 1, <= XENG_MAX_INTEGRATION        */
+} xeng_array_desc;
+
+enum {
+    XENG_OK        =  0,
+    XENG_EINVAL    = -1,  /* bad argument: size, null or misaligned pointer  */
+    XENG_ENOMEM    = -2,  /* device or host allocation failed                 */
+    XENG_EOVERFLOW = -3,  /* integration would exceed XENG_MAX_INTEGRATION    */
+    XENG_EDEVICE   = -4,  /* HIP runtime error; text in xeng_last_error       */
+    XENG_ESTATE    = -5   /* plan unusable after an earlier device error      */
+};
+
+enum {
+    XENG_DUMP_KEEP    = 1u << 0,  /* copy out but keep integrating             */
+    XENG_DUMP_TO_HOST = 1u << 1   /* dst are host pointers; call is synchronous */
+};
+
+/* Largest number of inputs per array the kernels are built for (the paper's
+ * largest design, eight boards of 32 inputs, Sec. 2.3). */
+#define XENG_MAX_INPUTS 256
+/* Largest integration (samples since the last dump) whose sums are
+ * guaranteed to fit int32: one sample adds at most 128 in magnitude
+ * (all codes -8), and (2^31 - 1) / 128 = 16,777,215. */
+#define XENG_MAX_INTEGRATION 16777215LL
+
+/*
+ * xeng_plan - create an engine for n_arrays independent arrays.
+ *   out        receives the plan (owned by the library; free with xeng_destroy).
+ *   arrays     n_arrays descriptors (read during the call only).
+ *   n_arrays   >= 1.  With one array this is the plain per-dump engine; with
+ *              more, every xeng_correlate call runs all arrays' work in one
+ *              batched launch (Sec. 2: each X node takes a band of channels;
+ *              Sec. 2.2: one GPU core per band - here many bands of many
+ *              arrays share one GPU).
+ *   flags      0 (reserved).
+ *   hip_stream hipStream_t to run on, or NULL for a stream the plan owns.
+ * Allocates the HBM-resident int32 accumulators (zeroed) and the batch
+ * work list.  Errors: EINVAL (null out/arrays, n_arrays < 1, N or F or
+ * max_time_per_call out of range), ENOMEM, EDEVICE.
+ */
+int xeng_plan(xeng_plan_t **out, const xeng_array_desc *arrays, int32_t n_arrays,
+              uint32_t flags, void *hip_stream);
+
+/*
+ * xeng_correlate - integrate one block of voltages per array (Sec. 2.2 CMAC,
+ * Sec. 1/2 integration).  Asynchronous on the plan's stream.
+ *   d_voltages  n_arrays device pointers, each uint8 [n_time[a]][F][N],
+ *               16-byte aligned; caller-owned, must stay valid until the
+ *               stream reaches this work.  May be NULL where n_time[a] == 0.
+ *   n_time      n_arrays sample counts; 0 skips that array.
+ * The block is added to the array's running integration.  Errors: EINVAL
+ * (null/misaligned pointer, n_time < 0 or > max_time_per_call), EOVERFLOW
+ * (samples since the last dump would exceed XENG_MAX_INTEGRATION; nothing is
+ * launched and the state is unchanged), EDEVICE, ESTATE.
+ */
+int xeng_correlate(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64_t *n_time);
+
+/*
+ * xeng_dump - hand out the integrated visibilities (Sec. 2.2: the CPU and
+ * disk threads take the GPU's output) and start a new integration.
+ *   array         index of the array, or -1 for all arrays.
+ *   dst           one pointer per dumped array (1, or n_arrays for -1), each
+ *                 int32 [F][N(N+1)/2][2]; device memory, or host memory with
+ *                 XENG_DUMP_TO_HOST.  Caller-owned.
+ *   flags         XENG_DUMP_KEEP: do not reset; XENG_DUMP_TO_HOST: see above.
+ *   n_integrated  optional out, one per dumped array: samples in the dump.
+ * Without KEEP the accumulators are zeroed and the sample count reset.
+ * Stream-ordered after all earlier correlate calls; with TO_HOST it waits for
+ * the copy before returning.  Errors: EINVAL, EDEVICE, ESTATE.
+ */
+int xeng_dump(xeng_plan_t *p, int32_t array, int32_t *const *dst, uint32_t flags,
+              int64_t *n_integrated);
+
+/* xeng_destroy - wait for the plan's work, free everything it owns.  NULL is a no-op. */
+void xeng_destroy(xeng_plan_t *p);
+
+/* Number of baselines N(N+1)/2 including autos; -1 if n < 0. */
+int64_t xeng_nbaselines(int32_t n);
+
+/* k(i,j) = i(i+1)/2 + j for 0 <= j <= i; -1 otherwise. */
+int64_t xeng_baseline_index(int32_t i, int32_t j);
+
+/* Static text for a status code. */
+const char *xeng_strerror(int status);
+
+/* Text of the plan's last error ("" if none); valid until the next call on p. */
+const char *xeng_last_error(const xeng_plan_t *p);
+
+/* Samples integrated since the last dump for one array; -1 on bad arguments. */
+int64_t xeng_integrated(const xeng_plan_t *p, int32_t array);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XENG_H */

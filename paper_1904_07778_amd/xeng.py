@@ -1,0 +1,211 @@
+"""ctypes binding of the X-engine C ABI (``include/xeng.h``), same names.
+
+Argument marshalling only: every step of the X-engine runs in the HIP
+library.  PyTorch supplies device memory (uint8 voltage tensors, int32
+visibility tensors) and streams.  There is no fallback: if ``libxeng.so``
+is missing or cannot be loaded, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("XENG_LIB", os.path.join(_HERE, "libxeng.so"))
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"X-engine library not built: {LIB_PATH} is missing "
+                      "(run __graft_entry__.build() or paper_1904_07778_amd/build.py)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+XENG_OK, XENG_EINVAL, XENG_ENOMEM, XENG_EOVERFLOW, XENG_EDEVICE, XENG_ESTATE = 0, -1, -2, -3, -4, -5
+XENG_DUMP_KEEP = 1 << 0
+XENG_DUMP_TO_HOST = 1 << 1
+XENG_MAX_INPUTS = 256
+XENG_MAX_INTEGRATION = 16_777_215
+
+
+class xeng_array_desc(ctypes.Structure):
+    _fields_ = [("n_inputs", ctypes.c_int32), ("n_chans", ctypes.c_int32),
+                ("max_time_per_call", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_lib.xeng_plan.argtypes = [ctypes.POINTER(_P), ctypes.POINTER(xeng_array_desc), ctypes.c_int32,
+                           ctypes.c_uint32, _P]
+_lib.xeng_plan.restype = ctypes.c_int
+_lib.xeng_correlate.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64)]
+_lib.xeng_correlate.restype = ctypes.c_int
+_lib.xeng_dump.argtypes = [_P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.c_uint32,
+                           ctypes.POINTER(ctypes.c_int64)]
+_lib.xeng_dump.restype = ctypes.c_int
+_lib.xeng_destroy.argtypes = [_P]
+_lib.xeng_destroy.restype = None
+_lib.xeng_nbaselines.argtypes = [ctypes.c_int32]
+_lib.xeng_nbaselines.restype = ctypes.c_int64
+_lib.xeng_baseline_index.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.xeng_baseline_index.restype = ctypes.c_int64
+_lib.xeng_strerror.argtypes = [ctypes.c_int]
+_lib.xeng_strerror.restype = ctypes.c_char_p
+_lib.xeng_last_error.argtypes = [_P]
+_lib.xeng_last_error.restype = ctypes.c_char_p
+_lib.xeng_integrated.argtypes = [_P, ctypes.c_int32]
+_lib.xeng_integrated.restype = ctypes.c_int64
+
+
+class XengError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        text = _lib.xeng_strerror(status).decode()
+        super().__init__(f"{text} ({status})" + (f": {msg}" if msg else ""))
+
+
+def _check(status: int, plan=None):
+    if status != XENG_OK:
+        msg = _lib.xeng_last_error(plan).decode() if plan else ""
+        raise XengError(status, msg)
+
+
+def _ptr(x) -> int | None:
+    """Raw address of a tensor/array/int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if hasattr(x, "ctypes"):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x).__name__}")
+
+
+# ----------------------------------------------------------- raw C entry points
+def xeng_plan(arrays: Sequence[tuple[int, int, int]], flags: int = 0, stream=None) -> int:
+    """arrays: (n_inputs, n_chans, max_time_per_call) per array; stream: torch
+    stream, raw hipStream_t int, or None (plan-owned stream).  Returns the handle."""
+    descs = (xeng_array_desc * len(arrays))(*[xeng_array_desc(*a) for a in arrays])
+    h = _P()
+    s = getattr(stream, "cuda_stream", stream)
+    _check(_lib.xeng_plan(ctypes.byref(h), descs, len(arrays), flags, s))
+    return h.value
+
+
+def xeng_correlate(plan: int, voltages: Sequence, n_time: Sequence[int]) -> None:
+    n = len(n_time)
+    ptrs = (_P * n)(*[_ptr(v) for v in voltages])
+    ts = (ctypes.c_int64 * n)(*n_time)
+    _check(_lib.xeng_correlate(plan, ptrs, ts), plan)
+
+
+def xeng_dump(plan: int, array: int, dst: Sequence, flags: int = 0) -> list[int]:
+    n = len(dst)
+    ptrs = (_P * n)(*[_ptr(d) for d in dst])
+    nint = (ctypes.c_int64 * n)()
+    _check(_lib.xeng_dump(plan, array, ptrs, flags, nint), plan)
+    return list(nint)
+
+
+def xeng_destroy(plan: int) -> None:
+    _lib.xeng_destroy(plan)
+
+
+def xeng_nbaselines(n: int) -> int:
+    return int(_lib.xeng_nbaselines(n))
+
+
+def xeng_baseline_index(i: int, j: int) -> int:
+    return int(_lib.xeng_baseline_index(i, j))
+
+
+def xeng_strerror(status: int) -> str:
+    return _lib.xeng_strerror(status).decode()
+
+
+def xeng_last_error(plan: int) -> str:
+    return _lib.xeng_last_error(plan).decode()
+
+
+def xeng_integrated(plan: int, array: int) -> int:
+    return int(_lib.xeng_integrated(plan, array))
+
+
+# ------------------------------------------------------------ tensor wrapper
+@dataclass
+class ArraySpec:
+    n_inputs: int
+    n_chans: int
+    max_time_per_call: int
+
+    @property
+    def nbl(self) -> int:
+        return self.n_inputs * (self.n_inputs + 1) // 2
+
+
+class Plan:
+    """Owns one C plan; checks tensor shapes/dtypes before handing pointers over."""
+
+    def __init__(self, arrays: Sequence[tuple[int, int, int]], stream=None):
+        """stream: a torch.cuda.Stream the engine runs on; by default a new one.
+        correlate() orders the engine after the caller's current stream, and
+        dump() orders the caller's current stream after the engine."""
+        import torch
+        self.specs = [ArraySpec(*a) for a in arrays]
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.handle = None
+        self.handle = xeng_plan([(s.n_inputs, s.n_chans, s.max_time_per_call) for s in self.specs],
+                                0, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            xeng_destroy(self.handle)
+            self.handle = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def correlate(self, voltages) -> None:
+        """voltages: one uint8 CUDA tensor [T, F, N] per array (None skips)."""
+        import torch
+        if len(voltages) != len(self.specs):
+            raise ValueError("one voltage tensor (or None) per array")
+        ptrs, ts = [], []
+        self.stream.wait_stream(torch.cuda.current_stream())
+        for v, s in zip(voltages, self.specs):
+            if v is None:
+                ptrs.append(None)
+                ts.append(0)
+                continue
+            if v.dtype != torch.uint8 or not v.is_cuda or not v.is_contiguous():
+                raise ValueError("voltages must be contiguous uint8 device tensors")
+            if v.dim() != 3 or v.shape[1] != s.n_chans or v.shape[2] != s.n_inputs:
+                raise ValueError(f"voltage block {tuple(v.shape)} does not match [T, {s.n_chans}, {s.n_inputs}]")
+            ptrs.append(v)
+            ts.append(v.shape[0])
+            v.record_stream(self.stream)
+        xeng_correlate(self.handle, ptrs, ts)
+
+    def new_output(self, array: int, host: bool = False):
+        import torch
+        s = self.specs[array]
+        return torch.empty((s.n_chans, s.nbl, 2), dtype=torch.int32,
+                           device="cpu" if host else "cuda", pin_memory=host)
+
+    def dump(self, array: int = -1, out=None, keep: bool = False, to_host: bool = False):
+        """Returns (list of int32 [F, nbl, 2] tensors, list of n_integrated)."""
+        import torch
+        idx = list(range(len(self.specs))) if array < 0 else [array]
+        if out is None:
+            out = [self.new_output(a, host=to_host) for a in idx]
+        self.stream.wait_stream(torch.cuda.current_stream())   # out may come from the caller's stream
+        flags = (XENG_DUMP_KEEP if keep else 0) | (XENG_DUMP_TO_HOST if to_host else 0)
+        n = xeng_dump(self.handle, array, out, flags)
+        if not to_host:
+            torch.cuda.current_stream().wait_stream(self.stream)
+        return out, n

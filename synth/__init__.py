@@ -59,11 +59,13 @@ def quantise(z: np.ndarray) -> np.ndarray:
 
 def pack(re: np.ndarray, im: np.ndarray) -> np.ndarray:
     """Pack 4-bit two's-complement (re, im) into one byte, re in the high nibble."""
-    re = np.asarray(re, dtype=np.int16)
-    im = np.asarray(im, dtype=np.int16)
+    re = np.asarray(re)
+    im = np.asarray(im)
     if re.size and (re.min() < -8 or re.max() > 7 or im.min() < -8 or im.max() > 7):
         raise ValueError("4-bit components must lie in [-8, 7]")
-    return (((re & 0xF) << 4) | (im & 0xF)).astype(np.uint8)
+    re8 = re.astype(np.int8).view(np.uint8)
+    im8 = im.astype(np.int8).view(np.uint8)
+    return ((re8 << 4) | (im8 & 0xF)).astype(np.uint8)
 
 
 @dataclass(frozen=True)
@@ -87,24 +89,27 @@ def _channel(recipe: str, seed: int, n_inputs: int, n_time: int, f: int,
     if recipe == "uniform":
         v = r.integers(-7, 8, size=(n_time, n_inputs, 2), dtype=np.int8)
         return pack(v[..., 0], v[..., 1])
-    g = r.standard_normal(size=(n_time, n_inputs, 2))
-    re = SIGMA * g[..., 0]
-    im = SIGMA * g[..., 1]
+    g = r.standard_normal(size=(n_time, n_inputs, 2), dtype=np.float32)
+    g *= np.float32(SIGMA)
+    re, im = g[..., 0], g[..., 1]
     if recipe == "tone":
+        # exp(j(2 pi nu t + theta_f + phi_i)) = exp(j(2 pi nu t + theta_f)) * exp(j phi_i)
         theta_f = r.uniform(0.0, 2 * np.pi)
         t = np.arange(n_time, dtype=np.float64) + float(block) * n_time
-        ph = 2 * np.pi * TONE_FREQ * t[:, None] + theta_f + params.phi_tone[None, :]
-        re = re + TONE_AMP * SIGMA * np.cos(ph)
-        im = im + TONE_AMP * SIGMA * np.sin(ph)
+        pt = np.exp(1j * (2 * np.pi * TONE_FREQ * t + theta_f)).astype(np.complex64)
+        pi_ = (TONE_AMP * SIGMA * np.exp(1j * params.phi_tone)).astype(np.complex64)
+        z = pt[:, None] * pi_[None, :]
+        re += z.real
+        im += z.imag
     elif recipe == "sources":
         k = max(0, min(n_src, len(SOURCE_AMPS)))
-        s = r.standard_normal(size=(n_time, k, 2)) * np.sqrt(0.5)
-        sc = s[..., 0] + 1j * s[..., 1]                               # [T, k]
-        gain = np.asarray(SOURCE_AMPS[:k]) * SIGMA                    # [k]
-        mix = gain[None, :] * np.exp(1j * params.phi_src[:, :k])      # [N, k]
-        z = sc @ mix.T                                                # [T, N]
-        re = re + z.real
-        im = im + z.imag
+        s = r.standard_normal(size=(n_time, k, 2), dtype=np.float32) * np.float32(np.sqrt(0.5))
+        sc = (s[..., 0] + 1j * s[..., 1]).astype(np.complex64)               # [T, k]
+        gain = np.asarray(SOURCE_AMPS[:k]) * SIGMA                             # [k]
+        mix = (gain[None, :] * np.exp(1j * params.phi_src[:, :k])).astype(np.complex64)  # [N, k]
+        z = sc @ mix.T                                                         # [T, N]
+        re += z.real
+        im += z.imag
     elif recipe != "noise":
         raise ValueError(f"unknown recipe {recipe!r}")
     return pack(quantise(re), quantise(im))

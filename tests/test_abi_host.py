@@ -1,0 +1,61 @@
+"""CPU-side checks of the C ABI library: it loads, exports every symbol the
+header declares, and its host-only helpers and argument checks behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xeng.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xeng_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("xeng_plan", "xeng_correlate", "xeng_dump", "xeng_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1904_07778_amd import xeng
+    lib = ctypes.CDLL(xeng.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_helpers():
+    from paper_1904_07778_amd import xeng as X
+    assert X.xeng_nbaselines(0) == 0 and X.xeng_nbaselines(-1) == -1
+    assert X.xeng_nbaselines(192) == 18528
+    k = 0
+    for i in range(20):
+        for j in range(i + 1):
+            assert X.xeng_baseline_index(i, j) == k
+            k += 1
+        assert X.xeng_baseline_index(i, i + 1) == -1
+    assert X.xeng_strerror(X.XENG_EOVERFLOW)
+    assert X.xeng_strerror(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("desc", [(0, 4, 10), (257, 4, 10), (8, 0, 10), (8, 4, 0), (8, 4, 16_777_216)])
+def test_plan_rejects_bad_shapes_before_touching_the_device(desc):
+    from paper_1904_07778_amd import xeng as X
+    with pytest.raises(X.XengError) as e:
+        X.xeng_plan([desc])
+    assert e.value.status == X.XENG_EINVAL
+
+
+def test_null_arguments():
+    from paper_1904_07778_amd import xeng as X
+    lib = X._lib
+    assert lib.xeng_plan(None, None, 1, 0, None) == X.XENG_EINVAL
+    assert lib.xeng_correlate(None, None, None) == X.XENG_EINVAL
+    assert lib.xeng_dump(None, 0, None, 0, None) == X.XENG_EINVAL
+    lib.xeng_destroy(None)
+    assert X.xeng_integrated(None, 0) == -1

@@ -1,0 +1,162 @@
+"""Bit-exact parity of the HIP X-engine against the CPU oracle.
+
+Integer work: every visibility must equal the oracle's exactly.  Sizes
+span several 16-row tiles with ragged edges in N and ragged tails in T; the
+full-size workloads are checked on sampled channels the oracle computes one
+by one, plus properties that hold at any size on every channel.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import first_mismatch, gpu_available, run_engine
+
+pytestmark = pytest.mark.gpu
+if not gpu_available():
+    pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="no GPU")]
+
+
+def check(v_blocks, N, F, chans=None, max_t=None):
+    got, n = run_engine(v_blocks, N, F, max_t=max_t)
+    assert n == sum(b.shape[0] for b in v_blocks)
+    e = oracle.Engine(N, F if chans is None else len(chans))
+    for b in v_blocks:
+        e.correlate(b if chans is None else np.ascontiguousarray(b[:, chans]))
+    want, _ = e.dump()
+    g = got if chans is None else got[chans]
+    assert np.array_equal(g, want), first_mismatch(g, want)
+    return got
+
+
+def test_dish_tiny_full():
+    w = synth.WORKLOADS["dish_tiny"]
+    v = synth.voltages(w["recipe"], w["seed"], w["n_inputs"], w["n_chans"], w["n_time"])
+    print(f"dish_tiny N={w['n_inputs']} F={w['n_chans']} T={w['n_time']}", flush=True)
+    check([v], w["n_inputs"], w["n_chans"])
+
+
+# every tile count 1..16, ragged N, ragged T tails, time-split and single-WG launches
+SWEEP = [(1, 1, 1), (2, 3, 31), (3, 5, 33), (5, 2, 100), (8, 7, 64), (15, 3, 257),
+         (16, 4, 1000), (17, 2, 95), (31, 9, 129), (32, 6, 4096), (33, 3, 333),
+         (47, 2, 520), (48, 5, 64), (63, 3, 127), (64, 4, 2048), (80, 2, 96),
+         (96, 3, 1024), (100, 2, 77), (112, 2, 300), (127, 1, 513), (128, 3, 1000),
+         (144, 2, 256), (150, 1, 99), (160, 2, 640), (176, 2, 160), (191, 1, 400),
+         (192, 3, 512), (200, 2, 200), (224, 1, 96), (240, 1, 1100), (255, 1, 65),
+         (256, 2, 384), (1, 1, 100000), (48, 1, 70000), (192, 1, 20000)]
+
+
+@pytest.mark.parametrize("N,F,T", SWEEP, ids=lambda x: str(x))
+def test_random_shape_sweep(N, F, T):
+    print(f"sweep N={N} F={F} T={T}", flush=True)
+    rng = np.random.default_rng(1000 * N + 10 * F + T % 10)
+    re = rng.integers(-8, 8, size=(T, F, N))
+    im = rng.integers(-8, 8, size=(T, F, N))
+    check([synth.pack(re, im)], N, F)
+
+
+@pytest.mark.parametrize("N", [17, 64, 192, 256])
+@pytest.mark.parametrize("pattern", ["all_minus8", "all_plus7", "alternating", "one_hot"])
+def test_adversarial_codes(N, pattern):
+    F, T = 3, 1000
+    print(f"adversarial {pattern} N={N}", flush=True)
+    if pattern == "all_minus8":
+        v = np.full((T, F, N), 0x88, np.uint8)
+    elif pattern == "all_plus7":
+        v = np.full((T, F, N), 0x77, np.uint8)
+    elif pattern == "alternating":
+        t, f, n = np.indices((T, F, N))
+        s = (t + n) % 2
+        v = np.where(s == 0, 0x77, 0x88).astype(np.uint8)
+        v[:, 1, ::3] = 0x8F   # -8 - 1j
+    else:
+        v = np.zeros((T, F, N), np.uint8)
+        v[::7, :, N // 2] = 0x80
+        v[::5, :, 0] = 0x08
+        v[::3, :, N - 1] = 0x71
+    check([v], N, F)
+
+
+def test_multi_call_integration_and_keep():
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    N, F = 70, 5
+    blocks = [synth.voltages("noise", 21, N, F, t, block=b) for b, t in enumerate([100, 257, 32, 1000])]
+    e = oracle.Engine(N, F)
+    with Plan([(N, F, 1000)]) as p:
+        for b in blocks[:2]:
+            p.correlate([torch.from_numpy(b).cuda()])
+            e.correlate(b)
+        out, n = p.dump(keep=True, to_host=True)
+        want, _ = e.dump(keep=True)
+        assert n == [357] and np.array_equal(out[0].numpy(), want)
+        for b in blocks[2:]:
+            p.correlate([torch.from_numpy(b).cuda()])
+            e.correlate(b)
+        out, n = p.dump(to_host=True)
+        want, _ = e.dump()
+        assert n == [1389] and np.array_equal(out[0].numpy(), want), first_mismatch(out[0].numpy(), want)
+        out, n = p.dump(to_host=True)
+        assert n == [0] and not out[0].numpy().any()
+        # after a dump the next call starts a fresh integration (store path)
+        p.correlate([torch.from_numpy(blocks[0]).cuda()])
+        out, n = p.dump(to_host=True)
+        assert np.array_equal(out[0].numpy(), oracle.correlate(blocks[0]))
+
+
+def test_dump_to_device_buffer():
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    N, F, T = 33, 4, 200
+    v = synth.voltages("tone", 3, N, F, T)
+    with Plan([(N, F, T)]) as p:
+        p.correlate([torch.from_numpy(v).cuda()])
+        out, n = p.dump()
+        assert out[0].is_cuda
+        assert np.array_equal(out[0].cpu().numpy(), oracle.correlate(v))
+
+
+def test_integration_exact_at_int32_bound():
+    """One input, all codes -8: the auto reaches 128 * 16,777,215 = 2,147,483,520,
+    the largest integration the library accepts, and must be exact."""
+    import torch
+    from paper_1904_07778_amd.xeng import XENG_EOVERFLOW, XENG_MAX_INTEGRATION, Plan, XengError
+    T = XENG_MAX_INTEGRATION
+    v = torch.full((T, 1, 1), 0x88, dtype=torch.uint8, device="cuda")
+    with Plan([(1, 1, T)]) as p:
+        p.correlate([v])
+        with pytest.raises(XengError) as ei:
+            p.correlate([v[:1]])
+        assert ei.value.status == XENG_EOVERFLOW
+        out, n = p.dump(to_host=True)
+    assert n == [T]
+    assert out[0].numpy().tolist() == [[[128 * T, 0]]]
+
+
+def test_dish_scale_eight_calls_sampled_channels():
+    w = synth.WORKLOADS["dish"]
+    N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
+    print(f"dish N={N} F={F} T={T} x {w['calls']} calls", flush=True)
+    blocks = [synth.voltages(w["recipe"], w["seed"], N, F, T, block=b) for b in range(w["calls"])]
+    chans = [0, 1, 2, 511, 512, 777, 1022, 1023]
+    got = check(blocks, N, F, chans=chans, max_t=T)
+    autos = got[:, [i * (i + 1) // 2 + i for i in range(N)]]
+    assert (autos[..., 1] == 0).all() and (autos[..., 0] >= 0).all()
+
+
+def test_cylinder_scale_sampled_channels():
+    w = synth.WORKLOADS["cylinder"]
+    N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
+    print(f"cylinder N={N} F={F} T={T}", flush=True)
+    v = synth.voltages(w["recipe"], w["seed"], N, F, T)
+    got, n = run_engine([v], N, F)
+    assert n == T
+    chans = [0, 1, 255, 256, 511, 512, 513, 1000, 1022, 1023]
+    for f in chans:
+        want = oracle.correlate(np.ascontiguousarray(v[:, f:f + 1]))
+        assert np.array_equal(got[f:f + 1], want), (f, first_mismatch(got[f:f + 1], want))
+    autos = got[:, [i * (i + 1) // 2 + i for i in range(N)]]
+    assert (autos[..., 1] == 0).all() and (autos[..., 0] > 0).all()
+    # Eq. 3: RMS = sqrt(P / 2N) of every input on every channel lies in 2..3
+    rms = np.sqrt(autos[..., 0] / (2 * T))
+    assert 2.0 < rms.mean() < 3.0
