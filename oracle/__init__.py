@@ -71,8 +71,14 @@ def lib():
             L.oracle_accumulate_c128.restype = ctypes.c_int
             L.oracle_to_int32.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
             L.oracle_to_int32.restype = ctypes.c_int64
+            L.oracle_max_threads.restype = ctypes.c_int
             _lib = L
     return _lib
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle uses when nthreads = 0."""
+    return int(lib().oracle_max_threads())
 
 
 def decode(byte: int) -> tuple[int, int]:

@@ -55,6 +55,16 @@ int64_t oracle_baseline_index(int32_t i, int32_t j)
     return (int64_t)i * (i + 1) / 2 + j;
 }
 
+/* Threads an OpenMP region of this library uses by default. */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static void set_threads(int nthreads)
 {
 #ifdef _OPENMP

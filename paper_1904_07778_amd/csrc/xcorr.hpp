@@ -27,10 +27,7 @@
 //   right after a dump, read-modify-write when one workgroup owns the
 //   channel, atomics when the time range is split over several workgroups.
 //
-// Work split inside a channel: the triangle has NT(NT+1)/2 tile pairs
-// (NT = ceil(N/16)); tile row I holds I+1 pairs.  Rows are dealt to the W
-// waves of the channel largest first, each to the least loaded wave, so the
-// waves' MFMA counts differ by at most one row.  Each wave keeps all of its
+// Work split inside a channel: see PairPlan below.  Each wave keeps all of its
 // accumulators in registers for the whole time range.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -42,28 +39,51 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
 constexpr int KS = 32;  // time samples per MFMA K step (64 int8 = 32 x (re, im))
+// The staging kernel sums exact int8 products (|Re|, |Im| <= 128 per sample),
+// so any range up to the library's integration limit fits int32.
+constexpr int64_t XENG_MAX_T_PER_WG_STAGE = 16777215;
 
-// Deal tile rows to waves, largest first, each to the least loaded wave.
+// Work split inside a channel: the NT(NT+1)/2 tile pairs (I, J), J <= I, of
+// the lower triangle, taken in row-major order, are cut into W contiguous runs
+// whose lengths differ by at most one; wave w of the channel owns run w as a
+// list of row segments (I, J0..J1).
+constexpr int PAIRS_PER_WAVE = 20;  // 160 accumulator registers per wave
+
 template <int NT, int W>
-struct RowPlan {
-  int nrows[W];
-  int rows[W][NT];
+struct PairPlan {
+  int nseg[W];          // rows touched by wave w
+  int segI[W][NT];      // tile row of each segment
+  int segJ0[W][NT];     // first tile column
+  int segJ1[W][NT];     // last tile column (inclusive)
   int npairs[W];
-  constexpr RowPlan() : nrows(), rows(), npairs() {
-    for (int I = NT - 1; I >= 0; --I) {
-      int best = 0;
-      for (int w = 1; w < W; ++w)
-        if (npairs[w] < npairs[best]) best = w;
-      rows[best][nrows[best]++] = I;
-      npairs[best] += I + 1;
+  int maxrow[W];
+  constexpr PairPlan() : nseg(), segI(), segJ0(), segJ1(), npairs(), maxrow() {
+    const int total = NT * (NT + 1) / 2;
+    for (int w = 0; w < W; ++w) {
+      const int b = w * total / W, e = (w + 1) * total / W;
+      npairs[w] = e - b;
+      maxrow[w] = -1;
+      int p = 0;
+      for (int I = 0; I < NT; ++I) {
+        for (int J = 0; J <= I; ++J, ++p) {
+          if (p < b || p >= e) continue;
+          if (nseg[w] > 0 && segI[w][nseg[w] - 1] == I) {
+            segJ1[w][nseg[w] - 1] = J;
+          } else {
+            segI[w][nseg[w]] = I;
+            segJ0[w][nseg[w]] = J;
+            segJ1[w][nseg[w]] = J;
+            ++nseg[w];
+          }
+          maxrow[w] = I;
+        }
+      }
     }
   }
-  constexpr int max_row(int w) const {
-    int m = -1;
-    for (int k = 0; k < nrows[w]; ++k) m = rows[w][k] > m ? rows[w][k] : m;
-    return m;
-  }
 };
+
+// Waves per channel that keep every wave within PAIRS_PER_WAVE tile pairs.
+constexpr int waves_for(int nt) { return (nt * (nt + 1) / 2 + PAIRS_PER_WAVE - 1) / PAIRS_PER_WAVE; }
 
 template <int NT, int W, int CPW>
 struct Cfg {
@@ -146,29 +166,30 @@ enum EpiMode : int {
 template <int NT, int W, int WC, int MODE, int NP>
 __device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v4i (&accR)[NP],
                                          const v4i (&accI)[NP]) {
-  constexpr RowPlan<NT, W> plan{};
-  constexpr int NR = plan.nrows[WC];
+  constexpr PairPlan<NT, W> plan{};
+  constexpr int NS = plan.nseg[WC];
   const int nbl = a.N * (a.N + 1) / 2;
   int32_t* accf = a.acc + (int64_t)f * nbl * 2;
   const int n = lane & 15;
   const int m0 = 4 * (lane >> 4);
   int idx = 0;
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    const int I = plan.rows[WC][k];
+  for (int sg = 0; sg < NS; ++sg) {
+    const int I = plan.segI[WC][sg];
+    const int J0 = plan.segJ0[WC][sg], J1 = plan.segJ1[WC][sg];
 #pragma unroll
     for (int vv = 0; vv < 4; ++vv) {
       const int i = 16 * I + m0 + vv;
       if (i >= a.N) continue;
       int32_t* rowp = accf + (i * (i + 1) / 2) * 2;
 #pragma unroll
-      for (int J = 0; J <= I; ++J) {
+      for (int J = J0; J <= J1; ++J) {
         const int j = 16 * J + n;
         if (J == I && j > i) continue;
         int32_t* dst = rowp + 2 * j;
         int re, im;
-        asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(re) : "a"(accR[idx + J][vv]));
-        asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(im) : "a"(accI[idx + J][vv]));
+        asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(re) : "a"(accR[idx + J - J0][vv]));
+        asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(im) : "a"(accI[idx + J - J0][vv]));
         if (MODE == EPI_ATOMIC) {
           atomicAdd(dst, re);
           atomicAdd(dst + 1, im);
@@ -180,17 +201,17 @@ __device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v
         }
       }
     }
-    idx += I + 1;
+    idx += J1 - J0 + 1;
   }
 }
 
 template <int NT, int W, int CPW, int WC>
 __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
   using C = Cfg<NT, W, CPW>;
-  constexpr RowPlan<NT, W> plan{};
+  constexpr PairPlan<NT, W> plan{};
   constexpr int NP = plan.npairs[WC];
-  constexpr int NR = plan.nrows[WC];
-  constexpr int NJ = plan.max_row(WC) + 1;
+  constexpr int NS = plan.nseg[WC];
+  constexpr int NJ = plan.maxrow[WC] + 1;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -267,12 +288,12 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
     for (int J = 0; J < NJ; ++J) p[J] = *reinterpret_cast<const v4i*>(pa + (frag0 + 16 * J) * 16);
     int idx = 0;
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int I = plan.rows[WC][k];
+    for (int sg = 0; sg < NS; ++sg) {
+      const int I = plan.segI[WC][sg];
       const v2i n = *reinterpret_cast<const v2i*>(na + (frag0 + 16 * I) * 8);
       const v4i q = v4i{p[I][2], p[I][3], n[0], n[1]};
 #pragma unroll
-      for (int J = 0; J <= I; ++J) {
+      for (int J = plan.segJ0[WC][sg]; J <= plan.segJ1[WC][sg]; ++J) {
         accR[idx] = __builtin_amdgcn_mfma_i32_16x16x64_i8(p[I], p[J], accR[idx], 0, 0, 0);
         accI[idx] = __builtin_amdgcn_mfma_i32_16x16x64_i8(q, p[J], accI[idx], 0, 0, 0);
         ++idx;

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <utility>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -18,38 +20,69 @@
 
 #include "../../include/xeng.h"
 #include "xcorr.hpp"
+#include "xcorr_ring.hpp"
 
 namespace {
 
 using LaunchFn = hipError_t (*)(dim3 grid, hipStream_t s, const xeng::Args& a);
 
 struct KernelInfo {
-  int nt, w, cpw, threads, lds_bytes;
+  int nt, w, cpw, stages, threads, lds_bytes;
+  int64_t max_t_per_wg;  // longest time range one workgroup may integrate
   LaunchFn launch;
 };
 
-template <int NT, int W, int CPW>
-hipError_t launch_xcorr(dim3 grid, hipStream_t s, const xeng::Args& a) {
-  using C = xeng::Cfg<NT, W, CPW>;
-  hipLaunchKernelGGL((xeng::xcorr_kernel<NT, W, CPW>), grid, dim3(C::THREADS), 0, s, a);
+// Staging kernel: any N (ragged edges), unpack once per workgroup into LDS.
+template <int NT>
+struct StageShape {
+  static constexpr int W = xeng::waves_for(NT);
+  static constexpr int CPW = W >= 4 ? 1 : 4 / W;
+};
+
+template <int NT>
+hipError_t launch_stage(dim3 grid, hipStream_t s, const xeng::Args& a) {
+  using SH = StageShape<NT>;
+  using C = xeng::Cfg<NT, SH::W, SH::CPW>;
+  hipLaunchKernelGGL((xeng::xcorr_kernel<NT, SH::W, SH::CPW>), grid, dim3(C::THREADS), 0, s, a);
   return hipGetLastError();
 }
 
-template <int NT, int W, int CPW>
-constexpr KernelInfo kinfo() {
-  using C = xeng::Cfg<NT, W, CPW>;
-  return KernelInfo{NT, W, CPW, C::THREADS, C::LDS_BYTES, &launch_xcorr<NT, W, CPW>};
+template <int NT>
+constexpr KernelInfo stage_info() {
+  using SH = StageShape<NT>;
+  using C = xeng::Cfg<NT, SH::W, SH::CPW>;
+  return KernelInfo{NT, SH::W, SH::CPW, 2, C::THREADS, C::LDS_BYTES, xeng::XENG_MAX_T_PER_WG_STAGE,
+                    &launch_stage<NT>};
 }
 
-// One configuration per tile count NT = ceil(N / 16): waves per channel W
-// keep each wave's accumulators (8 registers per tile pair) within about 320
-// registers; channels per workgroup CPW make a 4-wave workgroup.
-const KernelInfo kTable[] = {
-    kinfo<1, 1, 4>(),  kinfo<2, 1, 4>(),  kinfo<3, 1, 4>(),  kinfo<4, 1, 4>(),
-    kinfo<5, 1, 4>(),  kinfo<6, 1, 4>(),  kinfo<7, 1, 4>(),  kinfo<8, 1, 4>(),
-    kinfo<9, 2, 2>(),  kinfo<10, 2, 2>(), kinfo<11, 2, 2>(), kinfo<12, 2, 2>(),
-    kinfo<13, 4, 1>(), kinfo<14, 4, 1>(), kinfo<15, 4, 1>(), kinfo<16, 4, 1>(),
-};
+// Ring kernel: N a multiple of 16, direct-to-LDS ring + transposed reads.
+template <int NT>
+hipError_t launch_ring(dim3 grid, hipStream_t s, const xeng::Args& a) {
+  constexpr int W = xeng::waves_for(NT), CPW = xeng::ring_cpw(NT), S = xeng::ring_stages(NT);
+  using C = xeng::RingCfg<NT, W, CPW, S>;
+  hipLaunchKernelGGL((xeng::xcorr_ring_kernel<NT, W, CPW, S>), grid, dim3(C::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int NT>
+constexpr KernelInfo ring_info() {
+  constexpr int W = xeng::waves_for(NT), CPW = xeng::ring_cpw(NT), S = xeng::ring_stages(NT);
+  using C = xeng::RingCfg<NT, W, CPW, S>;
+  return KernelInfo{NT, W, CPW, S, C::THREADS, C::LDS_BYTES, xeng::RING_MAX_T_PER_WG, &launch_ring<NT>};
+}
+
+template <size_t... I>
+constexpr auto make_stage_table(std::index_sequence<I...>) {
+  return std::array<KernelInfo, sizeof...(I)>{stage_info<(int)I + 1>()...};
+}
+template <size_t... I>
+constexpr auto make_ring_table(std::index_sequence<I...>) {
+  return std::array<KernelInfo, sizeof...(I)>{ring_info<(int)I + 1>()...};
+}
+
+constexpr int kMaxTiles = XENG_MAX_INPUTS / 16;
+const auto kStage = make_stage_table(std::make_index_sequence<kMaxTiles>{});
+const auto kRing = make_ring_table(std::make_index_sequence<kMaxTiles>{});
 
 struct ArrayState {
   xeng_array_desc d{};
@@ -103,6 +136,7 @@ void grid_for(const xeng_plan_t* p, const ArrayState& s, int64_t T, dim3& grid, 
   const int64_t target = 2LL * p->n_cu;
   int64_t ts = (target + ngroups - 1) / ngroups;
   ts = std::max<int64_t>(1, std::min<int64_t>(ts, T / 256));
+  ts = std::max<int64_t>(ts, (T + s.k->max_t_per_wg - 1) / s.k->max_t_per_wg);
   t_chunk = (T + ts - 1) / ts;
   t_chunk = (t_chunk + xeng::KS - 1) / xeng::KS * xeng::KS;
   ts = (T + t_chunk - 1) / t_chunk;
@@ -175,7 +209,8 @@ int xeng_plan(xeng_plan_t** out, const xeng_array_desc* arrays, int32_t n_arrays
   for (int32_t a = 0; a < n_arrays; ++a) {
     ArrayState& s = p->arrays[a];
     s.d = arrays[a];
-    s.k = &kTable[(s.d.n_inputs + 15) / 16 - 1];
+    const int nt = (s.d.n_inputs + 15) / 16;
+    s.k = (s.d.n_inputs % 16 == 0) ? &kRing[nt - 1] : &kStage[nt - 1];
     s.acc_bytes = (size_t)s.d.n_chans * nbl_of(s.d.n_inputs) * 2 * sizeof(int32_t);
     e = hipMalloc(&s.acc, s.acc_bytes);
     if (e != hipSuccess) {
