@@ -1,0 +1,34 @@
+// kernels.hpp - the table of compiled X-engine kernels seen by the host code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xcorr.hpp"
+
+namespace xeng {
+
+using LaunchFn = hipError_t (*)(dim3 grid, hipStream_t s, const Args& a);
+
+struct KernelInfo {
+  int nt, w, cpw, stages, threads, lds_bytes;
+  int64_t max_t_per_wg;  // longest time range one workgroup may integrate
+  LaunchFn launch;
+};
+
+// Staging kernel (any N), by 16-row tile count nt = ceil(N/16), 1..16.
+const KernelInfo* stage_kernel(int nt);
+// 32-row-tile ring kernel, N a multiple of 16 up to 256 (one function per
+// translation unit; x32_kernel asks each).
+const KernelInfo* x32_kernel_a(int n);
+const KernelInfo* x32_kernel_b(int n);
+const KernelInfo* x32_kernel_c(int n);
+const KernelInfo* x32_kernel_d(int n);
+inline const KernelInfo* x32_kernel(int n) {
+  const KernelInfo* k = x32_kernel_a(n);
+  if (!k) k = x32_kernel_b(n);
+  if (!k) k = x32_kernel_c(n);
+  if (!k) k = x32_kernel_d(n);
+  return k;
+}
+
+}  // namespace xeng

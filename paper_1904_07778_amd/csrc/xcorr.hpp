@@ -37,6 +37,7 @@ namespace xeng {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int KS = 32;  // time samples per MFMA K step (64 int8 = 32 x (re, im))
 // The staging kernel sums exact int8 products (|Re|, |Im| <= 128 per sample),
@@ -140,6 +141,17 @@ __device__ __forceinline__ uint32_t load_group(const uint8_t* p, int navail, boo
   return w;
 }
 
+// Channel group of a workgroup.  Workgroups are dealt round-robin to the
+// eight XCDs (each with its own L2); this bijection on [0, groups) gives each
+// XCD a contiguous band of channel groups, so neighbouring channels, whose
+// rows share 128-byte lines in HBM, are fetched through the same L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_group(int b, int groups) {
+  const int q = groups / NUM_XCD, r = groups % NUM_XCD;
+  const int x = b % NUM_XCD, k = b / NUM_XCD;
+  return x * q + (x < r ? x : r) + k;
+}
+
 struct Args {
   const uint8_t* v;  // [T][F][N]
   int32_t* acc;      // [F][nbl][2]
@@ -217,7 +229,7 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
   const int lane = tid & 63;
   const int c = (tid >> 6) / W;               // channel slot of this wave
   const int r = lane & 15, g = lane >> 4;     // fragment row, 8-sample group
-  const int f0 = blockIdx.x * CPW;
+  const int f0 = xcd_group(blockIdx.x, gridDim.x) * CPW;
   const int64_t t_begin = (int64_t)blockIdx.y * a.t_chunk;
   const int64_t t_end = min(a.T, t_begin + a.t_chunk);
   if (t_end <= t_begin) return;  // uniform over the workgroup

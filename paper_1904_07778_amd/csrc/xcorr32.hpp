@@ -1,0 +1,436 @@
+// xcorr32.hpp - gfx950 X-engine kernel for N a multiple of 16 (32-row tiles).
+//
+// Result (paper Sec. 2 and Sec. 2.2): for each channel f of the grid and each
+// pair 0 <= j <= i < N, the exact int32 sum over the launch's time range of
+// x_i(t,f) conj(x_j(t,f)), added into acc[f][i(i+1)/2 + j].
+//
+// 1. HBM -> LDS ring.  Raw packed bytes go straight into an LDS ring of S
+//    stages with global_load_lds_dwordx4 (no registers; S-1 stages in
+//    flight).  A stage holds 64 time samples; its time row t holds the CPW*N
+//    bytes of the workgroup's channels ([c*N + i], as in HBM) in 16-byte
+//    chunks at a pitch of RPP chunks, RPP odd, so that 16 consecutive rows
+//    start on 16 different 16-byte bank groups (the spare chunk of a row is
+//    filled with a duplicate of its first chunk, which costs no HBM traffic).
+//
+// 2. Fragments.  ds_read_b64_tr_b8 transposes, in every 16-lane group, the
+//    8 x 16 byte block formed by the lanes' 8-byte reads.  Lane l of a wave
+//    reads time row 16h + 8(l/32) + ((l%16)/2), bytes 32J + 16((l/16)%2) +
+//    8(l%2) of its channel, and receives input 32J + (l%32) at the 8 times
+//    16h + 8(l/32) .. +7: one operand of v_mfma_i32_32x32x32_i8 (row l%32,
+//    K group l/32) for K-half h (16 samples) of a 32-sample step.
+//
+// 3. Unpack, scaled by 16 (no sign extension):
+//        re16 = w & 0xF0F0F0F0,   im16 = (w << 4) & 0xF0F0F0F0
+//    P = [re16 | im16] is the B operand of every product and the A operand
+//    of the real part; the imaginary part uses Q = [im16 | ~re16] (~x = -x-1,
+//    carry-free, and never overflows int8).  Summed over time:
+//        Re'_ij = 256 Re_ij,   Im'_ij = 256 Im_ij - 16 S_j,   S_j = sum_t im_j
+//    and Im_jj = 0 gives Im'_jj = -16 S_j, so the epilogue forms
+//        Re = Re' >> 8,   Im = (Im' - Im'_jj) >> 8   exactly.
+//    |Re'|, |Im'| <= 32896 per sample: a workgroup integrates at most
+//    MAX_T_PER_WG = 32768 samples (the host splits longer ranges).
+//
+// 4. Work split (UnitPlan).  A unit is the real or the imaginary product of
+//    one 32 x 32 tile pair (I, J), J <= I: 16 accumulator registers.  The
+//    NT(NT+1) units of a channel, in row-major order (I, then J, Re then
+//    Im), are cut into W contiguous runs; the runs one unit longer go to the
+//    first waves.  A workgroup has four waves, one per SIMD, each with up to
+//    11 units (176 accumulator registers); the next K-step's reads and
+//    unpacking are independent of the current step's MFMAs, so one wave
+//    keeps its SIMD's matrix core busy.  (For N > 192 eight waves of at
+//    most 9 units share the four SIMDs.)
+#pragma once
+#include <type_traits>
+
+#include "xcorr.hpp"
+
+namespace xeng {
+namespace x32 {
+
+constexpr int STAGE_T = 64;           // time samples per ring stage
+constexpr int MAX_T_PER_WG = 32768;   // int32 headroom of the x256 sums
+constexpr int MAX_UNITS_PER_WAVE = 11;
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+// 32-row tiles of an N-input channel and the launch shape for them.
+constexpr int tiles(int n) { return (n + 31) / 32; }
+constexpr int units(int nt) { return nt * (nt + 1); }
+constexpr int waves_per_channel(int nt) {
+  return units(nt) <= MAX_UNITS_PER_WAVE ? 1
+       : units(nt) <= 2 * MAX_UNITS_PER_WAVE ? 2
+       : units(nt) <= 4 * MAX_UNITS_PER_WAVE ? 4 : 8;
+}
+// Up to four waves per channel: one workgroup of four waves, one wave per
+// SIMD (up to 176 accumulator registers each).  Eight waves per channel
+// (N > 192): two waves per SIMD, at most 9 units (144 registers) each.
+constexpr int waves_per_wg(int nt) { return waves_per_channel(nt) <= 4 ? 4 : 8; }
+
+template <int NT, int W>
+struct UnitPlan {
+  static constexpr int U = units(NT);
+  static constexpr int MAXU = (U + W - 1) / W;
+  int nu[W];
+  int uI[W][MAXU];
+  int uJ[W][MAXU];
+  int uIm[W][MAXU];
+  bool needP[W][NT];   // tile read as an operand
+  bool needQ[W][NT];   // tile used as the row of an imaginary product
+  constexpr UnitPlan() : nu(), uI(), uJ(), uIm(), needP(), needQ() {
+    const int q = U / W, rem = U % W;
+    int u = 0, w = 0, k = 0;
+    for (int I = 0; I < NT; ++I)
+      for (int J = 0; J <= I; ++J)
+        for (int part = 0; part < 2; ++part) {
+          while (k == q + (w < rem ? 1 : 0)) {  // this wave's run is full
+            ++w;
+            k = 0;
+          }
+          uI[w][k] = I;
+          uJ[w][k] = J;
+          uIm[w][k] = part;
+          needP[w][I] = needP[w][J] = true;
+          if (part) needQ[w][I] = true;
+          ++k;
+          nu[w] = k;
+          ++u;
+        }
+  }
+};
+
+template <int N, int CPW, int S>
+struct Shape {
+  static constexpr int NT = tiles(N);
+  static constexpr int W = waves_per_channel(NT);
+  static constexpr int THREADS = 64 * W * CPW;
+  static constexpr int RPC = CPW * N / 16;            // 16-byte chunks of data per time row
+  static constexpr int RPP = RPC | 1;                 // odd row pitch in chunks
+  static constexpr int STAGE_BYTES = STAGE_T * RPP * 16;
+  static constexpr int LOADS = STAGE_BYTES / 1024;    // wave-wide 1 KB loads per stage (= RPP)
+  static constexpr int WAVES = W * CPW;
+  static constexpr int LPW_MAX = (LOADS + WAVES - 1) / WAVES;
+  static constexpr int LPW_MIN = LOADS / WAVES;
+  static constexpr int DIAG_BYTES = CPW * NT * 32 * 4;
+  static constexpr int LDS_BYTES = S * STAGE_BYTES > DIAG_BYTES ? S * STAGE_BYTES : DIAG_BYTES;
+  static_assert(N % 16 == 0, "N must be a multiple of 16");
+  static_assert(LOADS * 1024 == STAGE_BYTES, "a stage is whole 1 KB loads");
+  static_assert(S >= 2 && (S - 2) * LPW_MAX < 64, "ring depth");
+};
+
+// Launch shape per N: W waves per channel, CPW channels per workgroup, and
+// as many ring stages as fit 128 KB (3 to 8).
+constexpr int cpw_for(int n) { return waves_per_wg(tiles(n)) / waves_per_channel(tiles(n)); }
+constexpr int stages_for(int n) {
+  const int stage = STAGE_T * ((cpw_for(n) * n / 16) | 1) * 16;
+  const int s = (128 * 1024) / stage;
+  return s < 3 ? 3 : (s > 8 ? 8 : s);
+}
+
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 0xF) | ((n >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+// One wave-wide 1 KB load: lane i copies 16 bytes from gptr to LDS byte
+// address lds_base + 16 i (global_load_lds_dwordx4, base in M0).  Written as
+// asm so the compiler does not make every later LDS read wait for all loads
+// in flight; the ring waits for each stage with s_waitcnt vmcnt + barrier.
+// No register is written.  M0 is otherwise unused by this code (checked in
+// the generated assembly), so clobbering it is safe.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void lds_dma16(const uint8_t* gptr, uint32_t lds_base) {
+  asm volatile(
+      "s_mov_b32 m0, %1\n\t"
+      "global_load_lds_dwordx4 %0, off"
+      :
+      : "v"(gptr), "s"(lds_base)
+      : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+__device__ __forceinline__ uint32_t byte_mask(int n) {
+  return n >= 4 ? 0xFFFFFFFFu : (n <= 0 ? 0u : ((1u << (8 * n)) - 1u));
+}
+
+__device__ __forceinline__ v16i mfma32(v4i a, v4i b, v16i c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// Add one wave's tiles into the accumulator of channel f.  32x32 result
+// layout: lane l, register v hold row 8(v/4) + 4(l/32) + v%4, column l%32;
+// the 32 lanes of a half-wave write 32 consecutive baselines of one row.
+template <int N, int W, int WC, int MODE, int NU>
+__device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v16i (&acc)[NU],
+                                         const int32_t* dcol) {
+  constexpr int NT = tiles(N);
+  constexpr UnitPlan<NT, W> plan{};
+  constexpr int nbl = N * (N + 1) / 2;
+  int32_t* accf = a.acc + (int64_t)f * nbl * 2;
+  const int n = lane & 31;
+  const int mb = 4 * (lane >> 5);
+  sfor<0, NU>([&](auto u) {
+    constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u], IM = plan.uIm[WC][u];
+    const int j = 32 * J + n;
+    const int32_t bias = IM ? dcol[j] : 0;
+    sfor<0, 16>([&](auto v) {
+      const int i = 32 * I + 8 * (v / 4) + mb + (v % 4);
+      if ((N % 32 == 0 || i < N) && (J < I || j <= i)) {
+        int32_t* dst = accf + (i * (i + 1) / 2 + j) * 2 + IM;
+        int x;
+        asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(x) : "a"(acc[u][(int)v]));
+        x = (x - bias) >> 8;
+        if constexpr (MODE == EPI_ATOMIC)
+          atomicAdd(dst, x);
+        else if constexpr (MODE == EPI_ADD)
+          *dst += x;
+        else
+          *dst = x;
+      }
+    });
+  });
+}
+
+template <int N, int CPW, int S, int WC>
+__device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
+  using C = Shape<N, CPW, S>;
+  constexpr int NT = C::NT, W = C::W;
+  constexpr UnitPlan<NT, W> plan{};
+  constexpr int NU = plan.nu[WC];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int c = wave / W;
+  const int f0 = xcd_group(blockIdx.x, gridDim.x) * CPW;
+  const int64_t t_begin = (int64_t)blockIdx.y * a.t_chunk;
+  const int64_t t_end = min(a.T, t_begin + a.t_chunk);
+  if (t_end <= t_begin) return;  // uniform over the workgroup
+  const int nt = (int)(t_end - t_begin);
+  const int nstages = (nt + STAGE_T - 1) / STAGE_T;
+  const int64_t row_stride = (int64_t)a.F * N;
+  const int nch_valid = min(CPW, a.F - f0);  // the last group may be short of channels
+
+  // ---- producer: wave-wide loads q = wave, wave + WAVES, ... of every stage
+  const int my_loads = (C::LOADS - wave + C::WAVES - 1) / C::WAVES;
+  int64_t src_off[C::LPW_MAX];
+  int src_t[C::LPW_MAX];
+#pragma unroll
+  for (int k = 0; k < C::LPW_MAX; ++k) {
+    const int q = wave + k * C::WAVES;
+    const int slot = (q < C::LOADS ? q : 0) * 64 + lane;  // 16-byte LDS slot this lane fills
+    const int t = slot / C::RPP;                          // time row
+    int p = slot % C::RPP;                                // chunk within the row
+    if (p >= C::RPC) p = 0;                               // pitch padding: duplicate chunk 0
+    int ch = p / (N / 16);
+    const int kc = p % (N / 16);
+    if (ch >= nch_valid) ch = nch_valid - 1;              // channels past F: dropped later
+    src_t[k] = t;
+    src_off[k] = (int64_t)(f0 + ch) * N + 16 * kc;
+  }
+  auto issue_stage = [&](int st) {
+    const uint32_t base = lds_addr(lds) + (uint32_t)((st % S) * C::STAGE_BYTES);
+    const int64_t tb = t_begin + (int64_t)st * STAGE_T;
+#pragma unroll
+    for (int k = 0; k < C::LPW_MAX; ++k) {
+      const int q = wave + k * C::WAVES;
+      if (q < C::LOADS) {
+        int64_t tt = tb + src_t[k];
+        if (tt >= t_end) tt = t_end - 1;  // tail rows: valid bytes, zeroed by the reader
+        lds_dma16(a.v + tt * row_stride + src_off[k], __builtin_amdgcn_readfirstlane(base + q * 1024));
+      }
+    }
+  };
+
+  // ---- consumer
+  v16i acc[NU];
+  sfor<0, NU>([&](auto u) { acc[u] = v16i{}; });
+  const int G = lane >> 4;
+  // per-lane part of the transposed-read address within a stage
+  const int lane_off = (8 * (lane >> 5) + ((lane & 15) >> 1)) * C::RPP * 16 + 16 * (G & 1) + 8 * (lane & 1);
+  // lanes reading the empty upper half of a last, half-filled tile: they read
+  // the lower half instead (always inside the row) and zero the result
+  const bool upper_pad = (N % 32 == 16) && (G & 1);
+  const int pad_back = upper_pad ? 16 : 0;
+
+#pragma unroll
+  for (int st = 0; st < S - 1; ++st)
+    if (st < nstages) issue_stage(st);
+
+  // Wait for stage st (all waves' loads), then refill the slot of stage
+  // st-1, which every wave has finished reading: fragments are read one
+  // K-step ahead, so by this barrier the reads of stage st-1 are all done.
+  // In a last, partial stage the rows past the end hold duplicates of the
+  // last valid row; they are zeroed here so the readers need no masks.
+  auto enter_stage = [&](int st) {
+    // S-2 later stages are in flight in steady state; near the end wait for all
+    if (st + S - 2 < nstages) {
+      if (my_loads == C::LPW_MAX)
+        wait_vmcnt<(S - 2) * C::LPW_MAX>();
+      else
+        wait_vmcnt<(S - 2) * C::LPW_MIN>();
+    } else {
+      wait_vmcnt<0>();
+    }
+    __syncthreads();
+    const int valid_t = nt - st * STAGE_T;
+    if (valid_t < STAGE_T) {
+      uint8_t* slot = lds + (st % S) * C::STAGE_BYTES;
+      for (int i = valid_t * C::RPP + threadIdx.x; i < STAGE_T * C::RPP; i += C::THREADS)
+        *reinterpret_cast<v4i*>(slot + 16 * i) = v4i{0, 0, 0, 0};
+      __syncthreads();
+    }
+    if (st + S - 1 < nstages) issue_stage(st + S - 1);
+  };
+
+  // Transposed reads of the raw bytes of K-step ks of stage st (tile X, K-half h).
+  auto read_step = [&](int st, int ks, v2i (&raw)[NT][2]) {
+    const uint8_t* stage = lds + (st % S) * C::STAGE_BYTES + lane_off;
+    sfor<0, NT>([&](auto X) {
+      if constexpr (plan.needP[WC][X]) {
+        sfor<0, 2>([&](auto h) {
+          const uint8_t* p = stage + ((ks * 32 + 16 * h) * C::RPP + c * (N / 16) + 2 * X) * 16 -
+                             (X == NT - 1 ? pad_back : 0);
+          raw[X][h] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) v2i*)p);
+        });
+      }
+    });
+  };
+  // Unpack raw bytes into MFMA operands (x16 scaled re | im).
+  auto unpack = [&](const v2i (&raw)[NT][2], v4i (&P)[NT][2]) {
+    sfor<0, NT>([&](auto X) {
+      if constexpr (plan.needP[WC][X]) {
+        sfor<0, 2>([&](auto h) {
+          uint32_t w0 = (uint32_t)raw[X][h][0], w1 = (uint32_t)raw[X][h][1];
+          if constexpr (N % 32 == 16 && X == NT - 1) {
+            if (upper_pad) w0 = w1 = 0u;
+          }
+          P[X][h] = v4i{(int)(w0 & 0xF0F0F0F0u), (int)(w1 & 0xF0F0F0F0u),
+                        (int)((w0 << 4) & 0xF0F0F0F0u), (int)((w1 << 4) & 0xF0F0F0F0u)};
+        });
+      }
+    });
+  };
+  auto mfma_step = [&](const v4i (&P)[NT][2]) {
+    sfor<0, 2>([&](auto h) {
+      sfor<0, NU>([&](auto u) {
+        constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u];
+        if constexpr (plan.uIm[WC][u]) {
+          const v4i q = v4i{P[I][h][2], P[I][h][3], ~P[I][h][0], ~P[I][h][1]};
+          acc[u] = mfma32(q, P[J][h], acc[u]);
+        } else {
+          acc[u] = mfma32(P[I][h], P[J][h], acc[u]);
+        }
+      });
+    });
+  };
+
+  // Three-deep software pipeline over K-steps k (two per stage).  Block k
+  // issues the transposed reads of step k+2, unpacks step k+1 (read one
+  // block earlier, so already in registers) and runs step k's MFMAs; the
+  // three parts are independent and the scheduling groups interleave the
+  // unpack VALU with the MFMAs.  Blocks hold no branches: the stage entry
+  // (waits, barrier, DMA issue) sits between blocks and the last stage is
+  // peeled off.  Samples past the end of the range are zero (enter_stage),
+  // so whole K-steps are run.
+  static_assert(STAGE_T == 64, "two K-steps per stage");
+  constexpr int NTILE = [] {
+    int n = 0;
+    for (int x = 0; x < NT; ++x) n += plan.needP[WC][x] ? 1 : 0;
+    return n;
+  }();
+  constexpr int NREAD = 2 * NTILE;
+  constexpr int NMFMA = 2 * NU;
+  constexpr int VPM = (6 * NREAD + NMFMA - 1) / NMFMA + 1;  // VALU slots per MFMA
+  auto interleave = [&]() {
+    __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);  // transposed reads first
+    sfor<0, NMFMA>([&](auto) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, VPM, 0);  // then unpack VALU
+    });
+  };
+  v4i P0[NT][2], P1[NT][2];
+  v2i rawE[NT][2], rawO[NT][2];  // raw bytes of the even / odd K-step of a stage
+  enter_stage(0);
+  read_step(0, 0, rawE);
+  read_step(0, 1, rawO);
+  unpack(rawE, P0);
+  for (int st = 0; st + 1 < nstages; ++st) {
+    enter_stage(st + 1);
+    read_step(st + 1, 0, rawE);
+    unpack(rawO, P1);
+    mfma_step(P0);
+    interleave();
+    read_step(st + 1, 1, rawO);
+    unpack(rawE, P0);
+    mfma_step(P1);
+    interleave();
+  }
+  unpack(rawO, P1);
+  mfma_step(P0);
+  interleave();
+  mfma_step(P1);
+
+  // ---- epilogue: publish each column's Im' diagonal through LDS, then add
+  __syncthreads();  // the ring is no longer read
+  int32_t* diag = reinterpret_cast<int32_t*>(lds);  // [CPW][NT * 32]
+  sfor<0, NU>([&](auto u) {
+    constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u];
+    if constexpr (plan.uIm[WC][u] && I == J) {
+      // diagonal element (n, n) sits in the lanes with l/32 == (n%8)/4, register
+      // v = 4(n/8) + n%4
+      const int n = lane & 31;
+      if ((lane >> 5) == ((n & 7) >> 2)) {
+        sfor<0, 16>([&](auto v) {
+          if (v == 4 * (n >> 3) + (n & 3)) {
+            int d;
+            asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(d) : "a"(acc[u][(int)v]));
+            diag[c * NT * 32 + 32 * I + n] = d;
+          }
+        });
+      }
+    }
+  });
+  __syncthreads();
+  const int f = f0 + c;
+  if (f >= a.F) return;
+  const int32_t* dcol = diag + c * NT * 32;
+  if (a.mode == EPI_ATOMIC)
+    x32::epilogue<N, W, WC, EPI_ATOMIC>(a, f, lane, acc, dcol);
+  else if (a.mode == EPI_ADD)
+    x32::epilogue<N, W, WC, EPI_ADD>(a, f, lane, acc, dcol);
+  else
+    x32::epilogue<N, W, WC, EPI_STORE>(a, f, lane, acc, dcol);
+}
+
+template <int N, int CPW, int S, int WC>
+__device__ __forceinline__ void dispatch(int wc, const Args& a, uint8_t* lds) {
+  if constexpr (WC < Shape<N, CPW, S>::W) {
+    if (wc == WC)
+      x32::wave_main<N, CPW, S, WC>(a, lds);
+    else
+      x32::dispatch<N, CPW, S, WC + 1>(wc, a, lds);
+  }
+}
+
+template <int N, int CPW, int S>
+__global__ __launch_bounds__((Shape<N, CPW, S>::THREADS))
+__attribute__((amdgpu_waves_per_eu(Shape<N, CPW, S>::WAVES / 4))) void kernel(Args a) {
+  __shared__ __attribute__((aligned(1024))) uint8_t lds[Shape<N, CPW, S>::LDS_BYTES];
+  const int wc = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) % Shape<N, CPW, S>::W;
+  x32::dispatch<N, CPW, S, 0>(wc, a, lds);
+}
+
+}  // namespace x32
+}  // namespace xeng

@@ -8,8 +8,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <array>
-#include <utility>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -19,70 +17,11 @@
 #include <vector>
 
 #include "../../include/xeng.h"
-#include "xcorr.hpp"
-#include "xcorr_ring.hpp"
+#include "kernels.hpp"
 
 namespace {
 
-using LaunchFn = hipError_t (*)(dim3 grid, hipStream_t s, const xeng::Args& a);
-
-struct KernelInfo {
-  int nt, w, cpw, stages, threads, lds_bytes;
-  int64_t max_t_per_wg;  // longest time range one workgroup may integrate
-  LaunchFn launch;
-};
-
-// Staging kernel: any N (ragged edges), unpack once per workgroup into LDS.
-template <int NT>
-struct StageShape {
-  static constexpr int W = xeng::waves_for(NT);
-  static constexpr int CPW = W >= 4 ? 1 : 4 / W;
-};
-
-template <int NT>
-hipError_t launch_stage(dim3 grid, hipStream_t s, const xeng::Args& a) {
-  using SH = StageShape<NT>;
-  using C = xeng::Cfg<NT, SH::W, SH::CPW>;
-  hipLaunchKernelGGL((xeng::xcorr_kernel<NT, SH::W, SH::CPW>), grid, dim3(C::THREADS), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int NT>
-constexpr KernelInfo stage_info() {
-  using SH = StageShape<NT>;
-  using C = xeng::Cfg<NT, SH::W, SH::CPW>;
-  return KernelInfo{NT, SH::W, SH::CPW, 2, C::THREADS, C::LDS_BYTES, xeng::XENG_MAX_T_PER_WG_STAGE,
-                    &launch_stage<NT>};
-}
-
-// Ring kernel: N a multiple of 16, direct-to-LDS ring + transposed reads.
-template <int NT>
-hipError_t launch_ring(dim3 grid, hipStream_t s, const xeng::Args& a) {
-  constexpr int W = xeng::waves_for(NT), CPW = xeng::ring_cpw(NT), S = xeng::ring_stages(NT);
-  using C = xeng::RingCfg<NT, W, CPW, S>;
-  hipLaunchKernelGGL((xeng::xcorr_ring_kernel<NT, W, CPW, S>), grid, dim3(C::THREADS), 0, s, a);
-  return hipGetLastError();
-}
-
-template <int NT>
-constexpr KernelInfo ring_info() {
-  constexpr int W = xeng::waves_for(NT), CPW = xeng::ring_cpw(NT), S = xeng::ring_stages(NT);
-  using C = xeng::RingCfg<NT, W, CPW, S>;
-  return KernelInfo{NT, W, CPW, S, C::THREADS, C::LDS_BYTES, xeng::RING_MAX_T_PER_WG, &launch_ring<NT>};
-}
-
-template <size_t... I>
-constexpr auto make_stage_table(std::index_sequence<I...>) {
-  return std::array<KernelInfo, sizeof...(I)>{stage_info<(int)I + 1>()...};
-}
-template <size_t... I>
-constexpr auto make_ring_table(std::index_sequence<I...>) {
-  return std::array<KernelInfo, sizeof...(I)>{ring_info<(int)I + 1>()...};
-}
-
-constexpr int kMaxTiles = XENG_MAX_INPUTS / 16;
-const auto kStage = make_stage_table(std::make_index_sequence<kMaxTiles>{});
-const auto kRing = make_ring_table(std::make_index_sequence<kMaxTiles>{});
+using xeng::KernelInfo;
 
 struct ArrayState {
   xeng_array_desc d{};
@@ -210,7 +149,7 @@ int xeng_plan(xeng_plan_t** out, const xeng_array_desc* arrays, int32_t n_arrays
     ArrayState& s = p->arrays[a];
     s.d = arrays[a];
     const int nt = (s.d.n_inputs + 15) / 16;
-    s.k = (s.d.n_inputs % 16 == 0) ? &kRing[nt - 1] : &kStage[nt - 1];
+    s.k = (s.d.n_inputs % 16 == 0) ? xeng::x32_kernel(s.d.n_inputs) : xeng::stage_kernel(nt);
     s.acc_bytes = (size_t)s.d.n_chans * nbl_of(s.d.n_inputs) * 2 * sizeof(int32_t);
     e = hipMalloc(&s.acc, s.acc_bytes);
     if (e != hipSuccess) {
