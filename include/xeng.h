@@ -59,6 +59,10 @@ enum {
     XENG_DUMP_TO_HOST = 1u << 1   /* dst are host pointers; call is synchronous */
 };
 
+enum {
+    XENG_PLAN_BATCH   = 1u << 0   /* batched plan even with 0 or 1 arrays      */
+};
+
 /* Largest number of inputs per array the kernels are built for (the paper's
  * largest design, eight boards of 32 inputs, Sec. 2.3). */
 #define XENG_MAX_INPUTS 256
@@ -71,16 +75,21 @@ enum {
  * xeng_plan - create an engine for n_arrays independent arrays.
  *   out        receives the plan (owned by the library; free with xeng_destroy).
  *   arrays     n_arrays descriptors (read during the call only).
- *   n_arrays   >= 1.  With one array this is the plain per-dump engine; with
- *              more, every xeng_correlate call runs all arrays' work in one
- *              batched launch (Sec. 2: each X node takes a band of channels;
- *              Sec. 2.2: one GPU core per band - here many bands of many
- *              arrays share one GPU).
- *   flags      0 (reserved).
+ *   n_arrays   >= 1, or 0 with XENG_PLAN_BATCH (arrays attached later).
+ *              With one array (and no flag) this is the plain per-dump
+ *              engine: one kernel launch per xeng_correlate.  Otherwise the
+ *              plan is batched: every xeng_correlate runs the work of all its
+ *              arrays as one persistent launch over a work list of (array,
+ *              channel group, time chunk) items, recorded into a hipGraph
+ *              (Sec. 2: each X node takes a band of channels; Sec. 2.2: one
+ *              GPU core per band - here many bands of many arrays share one
+ *              GPU).  Results are bit-identical to the plain engine's.
+ *   flags      0 or XENG_PLAN_BATCH.
  *   hip_stream hipStream_t to run on, or NULL for a stream the plan owns.
- * Allocates the HBM-resident int32 accumulators (zeroed) and the batch
- * work list.  Errors: EINVAL (null out/arrays, n_arrays < 1, N or F or
- * max_time_per_call out of range), ENOMEM, EDEVICE.
+ * The array indices of later calls are slots 0 .. n_arrays-1 (see
+ * xeng_attach for more).  Allocates the HBM-resident int32 accumulators
+ * (zeroed).  Errors: EINVAL (null out, null arrays with n_arrays > 0, N or F
+ * or max_time_per_call out of range, unknown flags), ENOMEM, EDEVICE.
  */
 int xeng_plan(xeng_plan_t **out, const xeng_array_desc *arrays, int32_t n_arrays,
               uint32_t flags, void *hip_stream);
@@ -88,12 +97,17 @@ int xeng_plan(xeng_plan_t **out, const xeng_array_desc *arrays, int32_t n_arrays
 /*
  * xeng_correlate - integrate one block of voltages per array (Sec. 2.2 CMAC,
  * Sec. 1/2 integration).  Asynchronous on the plan's stream.
- *   d_voltages  n_arrays device pointers, each uint8 [n_time[a]][F][N],
- *               16-byte aligned; caller-owned, must stay valid until the
- *               stream reaches this work.  May be NULL where n_time[a] == 0.
- *   n_time      n_arrays sample counts; 0 skips that array.
- * The block is added to the array's running integration.  Errors: EINVAL
- * (null/misaligned pointer, n_time < 0 or > max_time_per_call), EOVERFLOW
+ *   d_voltages  one device pointer per slot (xeng_slots), each uint8
+ *               [n_time[a]][F][N], 16-byte aligned; caller-owned, must stay
+ *               valid until the stream reaches this work.  May be NULL where
+ *               n_time[a] == 0.
+ *   n_time      one sample count per slot; 0 skips that array (and must be 0
+ *               for a free slot).
+ * The block is added to the array's running integration.  A batched plan
+ * launches one captured graph per call; the graph keeps the pointers and
+ * counts of this call, so the caller may reuse its argument arrays at once.
+ * Errors: EINVAL (null/misaligned pointer, n_time < 0 or > max_time_per_call,
+ * n_time > 0 for a free slot), EOVERFLOW
  * (samples since the last dump would exceed XENG_MAX_INTEGRATION; nothing is
  * launched and the state is unchanged), EDEVICE, ESTATE.
  */
@@ -102,10 +116,13 @@ int xeng_correlate(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64
 /*
  * xeng_dump - hand out the integrated visibilities (Sec. 2.2: the CPU and
  * disk threads take the GPU's output) and start a new integration.
- *   array         index of the array, or -1 for all arrays.
- *   dst           one pointer per dumped array (1, or n_arrays for -1), each
- *                 int32 [F][N(N+1)/2][2]; device memory, or host memory with
- *                 XENG_DUMP_TO_HOST.  Caller-owned.
+ *   array         slot of the array, or -1 for all slots.
+ *   dst           one pointer per dumped slot (1, or xeng_slots for -1; free
+ *                 slots are skipped and their pointer ignored), each int32
+ *                 [F][N(N+1)/2][2]; device memory, or host memory with
+ *                 XENG_DUMP_TO_HOST.  Caller-owned.  8-byte aligned device
+ *                 destinations are written by one copy-and-clear kernel for
+ *                 all dumped arrays; others by a copy and a memset.
  *   flags         XENG_DUMP_KEEP: do not reset; XENG_DUMP_TO_HOST: see above.
  *   n_integrated  optional out, one per dumped array: samples in the dump.
  * Without KEEP the accumulators are zeroed and the sample count reset.
@@ -114,6 +131,48 @@ int xeng_correlate(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64
  */
 int xeng_dump(xeng_plan_t *p, int32_t array, int32_t *const *dst, uint32_t flags,
               int64_t *n_integrated);
+
+/*
+ * xeng_attach - add an array to a batched plan between calls (admission of a
+ * new sub-array into a running serving loop).
+ *   d      its descriptor (read during the call only).
+ *   index  receives its slot: the first free slot, else a new one at the end.
+ * Allocates and zeroes its accumulator of xeng_accumulator_bytes(N, F) bytes
+ * (hipMalloc).  Errors: EINVAL (plain plan, bad descriptor, null pointer),
+ * ENOMEM (the accumulator does not fit; the plan is unchanged), EDEVICE, ESTATE.
+ */
+int xeng_attach(xeng_plan_t *p, const xeng_array_desc *d, int32_t *index);
+
+/*
+ * xeng_detach - remove an array from a plan and free its accumulator.  Waits
+ * for the plan's stream first (dump the array before detaching it).  The
+ * slot is free afterwards: n_time must be 0 for it and dumps skip it.
+ * Errors: EINVAL (slot out of range or free), EDEVICE, ESTATE.
+ */
+int xeng_detach(xeng_plan_t *p, int32_t index);
+
+/* Number of slots of the plan (attached or free); -1 for NULL. */
+int32_t xeng_slots(const xeng_plan_t *p);
+
+/* Bytes of one array's accumulator, F * N(N+1)/2 * 2 * 4; -1 on bad sizes. */
+int64_t xeng_accumulator_bytes(int32_t n_inputs, int32_t n_chans);
+
+/*
+ * xeng_autotune - pick launch shapes by timing them on the caller's data.
+ *   d_voltages, n_time  one call's arguments, as for xeng_correlate.
+ *   reps                calls timed per candidate (>= 1).
+ *   best_ms             optional out: mean time of one call with the choice.
+ * Batched plan: the work-item granularity of the persistent launch (about
+ * 1, 2, 4 or 8 items per compute unit; items are cut along time).  Plain
+ * plan, per array: the tile shape (32-row tiles of the ring kernel, N a
+ * multiple of 16, or 16-row tiles of the staging kernel) and the number of
+ * workgroups per compute unit that the time split aims for.  The choice is
+ * kept by the plan for later calls.  Every accumulator must be freshly dumped
+ * (or never used); the trial sums are discarded and the accumulators are zero
+ * on return.  Synchronous.  Errors: EINVAL, EDEVICE, ESTATE.
+ */
+int xeng_autotune(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64_t *n_time,
+                  int32_t reps, float *best_ms);
 
 /* xeng_destroy - wait for the plan's work, free everything it owns.  NULL is a no-op. */
 void xeng_destroy(xeng_plan_t *p);
@@ -130,7 +189,8 @@ const char *xeng_strerror(int status);
 /* Text of the plan's last error ("" if none); valid until the next call on p. */
 const char *xeng_last_error(const xeng_plan_t *p);
 
-/* Samples integrated since the last dump for one array; -1 on bad arguments. */
+/* Samples integrated since the last dump for one array; -1 on bad arguments
+ * or a free slot. */
 int64_t xeng_integrated(const xeng_plan_t *p, int32_t array);
 
 #ifdef __cplusplus

@@ -202,19 +202,22 @@ __device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v
   });
 }
 
+// One work item: channel group `group` (channels CPW*group ..) over time
+// chunk `tchunk` (samples tchunk*t_chunk ..) of the call described by a.
+// tid is threadIdx.x (passed in so that a persistent caller can keep the
+// per-lane set-up from being hoisted out of its item loop).
 template <int N, int CPW, int S, int WC>
-__device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
+__device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group, int tchunk, int tid) {
   using C = Shape<N, CPW, S>;
   constexpr int NT = C::NT, W = C::W;
   constexpr UnitPlan<NT, W> plan{};
   constexpr int NU = plan.nu[WC];
 
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int c = wave / W;
-  const int f0 = xcd_group(blockIdx.x, gridDim.x) * CPW;
-  const int64_t t_begin = (int64_t)blockIdx.y * a.t_chunk;
+  const int f0 = group * CPW;
+  const int64_t t_begin = (int64_t)tchunk * a.t_chunk;
   const int64_t t_end = min(a.T, t_begin + a.t_chunk);
   if (t_end <= t_begin) return;  // uniform over the workgroup
   const int nt = (int)(t_end - t_begin);
@@ -287,7 +290,7 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
     const int valid_t = nt - st * STAGE_T;
     if (valid_t < STAGE_T) {
       uint8_t* slot = lds + (st % S) * C::STAGE_BYTES;
-      for (int i = valid_t * C::RPP + threadIdx.x; i < STAGE_T * C::RPP; i += C::THREADS)
+      for (int i = valid_t * C::RPP + tid; i < STAGE_T * C::RPP; i += C::THREADS)
         *reinterpret_cast<v4i*>(slot + 16 * i) = v4i{0, 0, 0, 0};
       __syncthreads();
     }
@@ -415,13 +418,22 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
 }
 
 template <int N, int CPW, int S, int WC>
-__device__ __forceinline__ void dispatch(int wc, const Args& a, uint8_t* lds) {
+__device__ __forceinline__ void dispatch(int wc, const Args& a, uint8_t* lds, int group, int tchunk,
+                                         int tid) {
   if constexpr (WC < Shape<N, CPW, S>::W) {
     if (wc == WC)
-      x32::wave_main<N, CPW, S, WC>(a, lds);
+      x32::wave_main<N, CPW, S, WC>(a, lds, group, tchunk, tid);
     else
-      x32::dispatch<N, CPW, S, WC + 1>(wc, a, lds);
+      x32::dispatch<N, CPW, S, WC + 1>(wc, a, lds, group, tchunk, tid);
   }
+}
+
+// One work item of an N-input array with the launch shape built for N.
+template <int N>
+__device__ __forceinline__ void run_item(const Args& a, uint8_t* lds, int group, int tchunk, int tid) {
+  constexpr int CPW = cpw_for(N), S = stages_for(N);
+  const int wc = __builtin_amdgcn_readfirstlane(tid >> 6) % Shape<N, CPW, S>::W;
+  x32::dispatch<N, CPW, S, 0>(wc, a, lds, group, tchunk, tid);
 }
 
 template <int N, int CPW, int S>
@@ -429,7 +441,7 @@ __global__ __launch_bounds__((Shape<N, CPW, S>::THREADS))
 __attribute__((amdgpu_waves_per_eu(Shape<N, CPW, S>::WAVES / 4))) void kernel(Args a) {
   __shared__ __attribute__((aligned(1024))) uint8_t lds[Shape<N, CPW, S>::LDS_BYTES];
   const int wc = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) % Shape<N, CPW, S>::W;
-  x32::dispatch<N, CPW, S, 0>(wc, a, lds);
+  x32::dispatch<N, CPW, S, 0>(wc, a, lds, xcd_group(blockIdx.x, gridDim.x), blockIdx.y, threadIdx.x);
 }
 
 }  // namespace x32

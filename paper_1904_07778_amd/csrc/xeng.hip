@@ -1,13 +1,17 @@
 // xeng.hip - host side of the X-engine C ABI (declared in include/xeng.h).
 //
-// A plan holds, per array, the HBM-resident int32 accumulator [F][nbl][2],
-// the number of samples integrated since the last dump, and the kernel
-// configuration chosen for its N.  xeng_correlate validates, applies the
-// overflow guard and launches; xeng_dump copies the accumulator out and
-// clears it on the plan's stream.
+// A plan holds, per array slot, the HBM-resident int32 accumulator
+// [F][nbl][2], the number of samples integrated since the last dump, and the
+// kernel configuration chosen for its N.  xeng_correlate validates, applies
+// the overflow guard and launches: one launch per array in a plain plan, one
+// captured graph around the persistent batch kernel in a batched plan.
+// xeng_dump copies the accumulators out and clears them on the plan's
+// stream.  Slots can be attached and detached between calls (admission in a
+// serving loop).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -17,6 +21,7 @@
 #include <vector>
 
 #include "../../include/xeng.h"
+#include "batch.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -25,11 +30,13 @@ using xeng::KernelInfo;
 
 struct ArrayState {
   xeng_array_desc d{};
+  bool active = false;  // slot holds an array (attached, not detached)
   int32_t* acc = nullptr;
   size_t acc_bytes = 0;
   int64_t n_integrated = 0;
   bool clean = true;  // accumulator is all zero (no launch since the last clear)
-  const KernelInfo* k = nullptr;
+  const KernelInfo* k = nullptr;  // kernel of the plain launch
+  int split = 2;                  // plain launch: aim for split * n_cu workgroups
 };
 
 }  // namespace
@@ -40,7 +47,16 @@ struct xeng_plan_s {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool dead = false;
+  bool batched = false;   // calls go through the persistent batch launch
+  int batch_split = 2;    // batch: about batch_split items per workgroup
   std::vector<ArrayState> arrays;
+  int32_t* counters = nullptr;  // batch queue heads, zero between launches
+  // Ring of instantiated graphs of batched calls, each with the event of its
+  // last launch (a graph is updated only once that launch has completed).
+  static constexpr int GRAPH_RING = 4;
+  hipGraphExec_t exec[GRAPH_RING] = {};
+  hipEvent_t done[GRAPH_RING] = {};
+  int next_graph = 0;
   std::string err;
 };
 
@@ -72,7 +88,7 @@ int64_t nbl_of(int32_t n) { return (int64_t)n * (n + 1) / 2; }
 void grid_for(const xeng_plan_t* p, const ArrayState& s, int64_t T, dim3& grid, int64_t& t_chunk,
               int& mode) {
   const int ngroups = (s.d.n_chans + s.k->cpw - 1) / s.k->cpw;
-  const int64_t target = 2LL * p->n_cu;
+  const int64_t target = (int64_t)s.split * p->n_cu;
   int64_t ts = (target + ngroups - 1) / ngroups;
   ts = std::max<int64_t>(1, std::min<int64_t>(ts, T / 256));
   ts = std::max<int64_t>(ts, (T + s.k->max_t_per_wg - 1) / s.k->max_t_per_wg);
@@ -81,6 +97,240 @@ void grid_for(const xeng_plan_t* p, const ArrayState& s, int64_t T, dim3& grid, 
   ts = (T + t_chunk - 1) / t_chunk;
   grid = dim3((unsigned)ngroups, (unsigned)ts, 1);
   mode = ts > 1 ? xeng::EPI_ATOMIC : (s.clean ? xeng::EPI_STORE : xeng::EPI_ADD);
+}
+
+
+bool valid_desc(const xeng_array_desc& d) {
+  return d.n_inputs >= 1 && d.n_inputs <= XENG_MAX_INPUTS && d.n_chans >= 1 &&
+         d.max_time_per_call >= 1 && d.max_time_per_call <= XENG_MAX_INTEGRATION;
+}
+
+// Default kernel for N: 32-row ring kernel when N is a multiple of 16, else
+// the staging kernel of 16-row tiles.
+const KernelInfo* default_kernel(int32_t n) {
+  return (n % 16 == 0) ? xeng::x32_kernel(n) : xeng::stage_kernel((n + 15) / 16);
+}
+
+int init_slot(xeng_plan_t* p, ArrayState& s, const xeng_array_desc& d) {
+  s = ArrayState{};
+  s.d = d;
+  s.k = default_kernel(d.n_inputs);
+  s.acc_bytes = (size_t)d.n_chans * nbl_of(d.n_inputs) * 2 * sizeof(int32_t);
+  hipError_t e = hipMalloc(&s.acc, s.acc_bytes);
+  if (e != hipSuccess) {
+    s.acc = nullptr;
+    return e == hipErrorOutOfMemory ? fail(p, XENG_ENOMEM, "accumulator of %zu bytes", s.acc_bytes)
+                                    : hip_fail(p, e, "accumulator allocation");
+  }
+  e = hipMemsetAsync(s.acc, 0, s.acc_bytes, p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "accumulator clear");
+  s.active = true;
+  return XENG_OK;
+}
+
+xeng::Args base_args(const ArrayState& s, const uint8_t* v, int64_t T) {
+  xeng::Args a{};
+  a.v = v;
+  a.acc = s.acc;
+  a.T = T;
+  a.F = s.d.n_chans;
+  a.N = s.d.n_inputs;
+  return a;
+}
+
+int launch_plain(xeng_plan_t* p, ArrayState& s, const uint8_t* v, int64_t T) {
+  xeng::Args args = base_args(s, v, T);
+  dim3 grid;
+  grid_for(p, s, T, grid, args.t_chunk, args.mode);
+  hipError_t e = s.k->launch(grid, p->stream, args);
+  return e == hipSuccess ? XENG_OK : hip_fail(p, e, "kernel launch");
+}
+
+// Batched call.  Arrays whose N the batch kernel covers become items of one
+// persistent launch (several when there are more than batch::MAX_ARRAYS);
+// the rest get their plain launch.  Per array the time range is cut into
+// chunks so that the items come to about batch_split per workgroup, from a
+// cost model of the kernel (the larger of its MFMA cycles and its HBM bytes
+// per sample, plus a fixed start-up cost per item); arrays are queued longest
+// item first.
+constexpr double ITEM_START_CYCLES = 4000.0;  // ring fill and epilogue of one item
+constexpr double HBM_BYTES_PER_CYCLE = 13.0;  // 8 TB/s over 256 CUs at 2.4 GHz
+
+double cycles_per_sample(const KernelInfo* k, int32_t n) {
+  const int nt = (n + 31) / 32;
+  const double mfma = (double)nt * (nt + 1) * k->cpw / 2.0;  // 32 cycles per 32 samples per unit, 4 SIMDs
+  const double hbm = (double)k->cpw * n / HBM_BYTES_PER_CYCLE;
+  return mfma > hbm ? mfma : hbm;
+}
+
+struct BatchEntry {
+  int32_t a;
+  int32_t ngroups, nchunks;
+  int64_t t_chunk;
+  double item_cycles;
+};
+
+int record_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_time) {
+  std::vector<BatchEntry> items;
+  std::vector<int32_t> others;
+  double total = 0;
+  for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) {
+    const ArrayState& s = p->arrays[a];
+    if (!s.active || n_time[a] == 0) continue;
+    if (!xeng::batch::supports(s.d.n_inputs) || s.k != xeng::x32_kernel(s.d.n_inputs)) {
+      others.push_back(a);
+      continue;
+    }
+    BatchEntry b{};
+    b.a = a;
+    b.ngroups = (s.d.n_chans + s.k->cpw - 1) / s.k->cpw;
+    total += (double)b.ngroups * (n_time[a] * cycles_per_sample(s.k, s.d.n_inputs) + ITEM_START_CYCLES);
+    items.push_back(b);
+  }
+  const double target = total / ((double)std::max(1, p->batch_split) * p->n_cu);
+  for (BatchEntry& b : items) {
+    const ArrayState& s = p->arrays[b.a];
+    const int64_t T = n_time[b.a];
+    const double full = T * cycles_per_sample(s.k, s.d.n_inputs);
+    int64_t nc = (int64_t)std::ceil(full / std::max(target, 1.0));
+    nc = std::max<int64_t>(1, std::min<int64_t>(nc, T / 256));
+    nc = std::max<int64_t>(nc, (T + s.k->max_t_per_wg - 1) / s.k->max_t_per_wg);
+    int64_t tc = (T + nc - 1) / nc;
+    tc = (tc + xeng::KS - 1) / xeng::KS * xeng::KS;
+    b.t_chunk = tc;
+    b.nchunks = (int32_t)((T + tc - 1) / tc);
+    b.item_cycles = tc * cycles_per_sample(s.k, s.d.n_inputs) + ITEM_START_CYCLES;
+  }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const BatchEntry& x, const BatchEntry& y) { return x.item_cycles > y.item_cycles; });
+  for (size_t first = 0; first < items.size(); first += xeng::batch::MAX_ARRAYS) {
+    xeng::batch::Params bp{};
+    bp.counters = p->counters;
+    int64_t n_items = 0;
+    const size_t last = std::min(items.size(), first + xeng::batch::MAX_ARRAYS);
+    for (size_t i = first; i < last; ++i) {
+      const BatchEntry& b = items[i];
+      const ArrayState& s = p->arrays[b.a];
+      const int k = bp.n_arrays++;
+      bp.arr[k] = base_args(s, v[b.a], n_time[b.a]);
+      bp.arr[k].t_chunk = b.t_chunk;
+      bp.arr[k].mode = b.nchunks > 1 ? xeng::EPI_ATOMIC : (s.clean ? xeng::EPI_STORE : xeng::EPI_ADD);
+      bp.ngroups[k] = b.ngroups;
+      bp.nchunks[k] = b.nchunks;
+      n_items += (int64_t)b.ngroups * b.nchunks;
+    }
+    const int grid = (int)std::min<int64_t>(p->n_cu, n_items);
+    hipError_t e = xeng::batch::launch(grid, p->stream, bp);
+    if (e != hipSuccess) return hip_fail(p, e, "batch kernel launch");
+  }
+  for (int32_t a : others) {
+    const int st = launch_plain(p, p->arrays[a], v[a], n_time[a]);
+    if (st != XENG_OK) return st;
+  }
+  return XENG_OK;
+}
+
+// Record the batched call into a graph on the plan's stream (stream capture),
+// then launch it.  Instantiated graphs are kept in a ring and updated in place
+// for later calls (hipGraphExecUpdate; a fresh instantiation if the update is
+// refused); a graph is updated only after its previous launch has completed,
+// so a launch in flight never sees new parameters.
+int run_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_time) {
+  const int slot = p->next_graph;
+  p->next_graph = (slot + 1) % xeng_plan_s::GRAPH_RING;
+  hipError_t e;
+  if (!p->done[slot]) {
+    e = hipEventCreateWithFlags(&p->done[slot], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(p, e, "graph event");
+  } else {
+    e = hipEventSynchronize(p->done[slot]);
+    if (e != hipSuccess) return hip_fail(p, e, "graph event wait");
+  }
+  e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_fail(p, e, "begin capture");
+  const int st = record_batched(p, v, n_time);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->stream, &graph);
+  if (st != XENG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(p, e, "end capture");
+  if (p->exec[slot]) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res;
+    if (hipGraphExecUpdate(p->exec[slot], graph, &err_node, &res) != hipSuccess ||
+        res != hipGraphExecUpdateSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(p->exec[slot]);
+      p->exec[slot] = nullptr;
+    }
+  }
+  if (!p->exec[slot]) {
+    e = hipGraphInstantiate(&p->exec[slot], graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      p->exec[slot] = nullptr;
+      (void)hipGraphDestroy(graph);
+      return hip_fail(p, e, "graph instantiate");
+    }
+  }
+  (void)hipGraphDestroy(graph);
+  e = hipGraphLaunch(p->exec[slot], p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "graph launch");
+  e = hipEventRecord(p->done[slot], p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "graph event record");
+  return XENG_OK;
+}
+
+int zero_accumulators(xeng_plan_t* p) {
+  for (ArrayState& s : p->arrays) {
+    if (!s.active) continue;
+    hipError_t e = hipMemsetAsync(s.acc, 0, s.acc_bytes, p->stream);
+    if (e != hipSuccess) return hip_fail(p, e, "accumulator clear");
+    s.clean = true;
+    s.n_integrated = 0;
+  }
+  return XENG_OK;
+}
+
+int validate_call(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_t* n_time) {
+  for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) {
+    const ArrayState& s = p->arrays[a];
+    const int64_t T = n_time[a];
+    if (!s.active) {
+      if (T != 0) return fail(p, XENG_EINVAL, "slot %d holds no array but n_time is %lld", a, (long long)T);
+      continue;
+    }
+    if (T < 0 || T > s.d.max_time_per_call)
+      return fail(p, XENG_EINVAL, "array %d: n_time %lld outside [0, %lld]", a, (long long)T,
+                  (long long)s.d.max_time_per_call);
+    if (T > 0 && (!d_voltages || !d_voltages[a] || !aligned16(d_voltages[a])))
+      return fail(p, XENG_EINVAL, "array %d: voltage pointer null or not 16-byte aligned", a);
+    if (s.n_integrated + T > XENG_MAX_INTEGRATION)
+      return fail(p, XENG_EOVERFLOW, "array %d: %lld + %lld samples exceed %lld", a,
+                  (long long)s.n_integrated, (long long)T, (long long)XENG_MAX_INTEGRATION);
+  }
+  return XENG_OK;
+}
+
+int correlate_unchecked(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_t* n_time) {
+  if (p->batched) {
+    const int st = run_batched(p, d_voltages, n_time);
+    if (st != XENG_OK) return st;
+  } else {
+    for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) {
+      if (!p->arrays[a].active || n_time[a] == 0) continue;
+      const int st = launch_plain(p, p->arrays[a], d_voltages[a], n_time[a]);
+      if (st != XENG_OK) return st;
+    }
+  }
+  for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) {
+    ArrayState& s = p->arrays[a];
+    if (!s.active || n_time[a] == 0) continue;
+    s.n_integrated += n_time[a];
+    s.clean = false;
+  }
+  return XENG_OK;
 }
 
 }  // namespace
@@ -109,22 +359,28 @@ const char* xeng_strerror(int status) {
 const char* xeng_last_error(const xeng_plan_t* p) { return p ? p->err.c_str() : ""; }
 
 int64_t xeng_integrated(const xeng_plan_t* p, int32_t array) {
-  if (!p || array < 0 || array >= (int32_t)p->arrays.size()) return -1;
+  if (!p || array < 0 || array >= (int32_t)p->arrays.size() || !p->arrays[array].active) return -1;
   return p->arrays[array].n_integrated;
+}
+
+int32_t xeng_slots(const xeng_plan_t* p) { return p ? (int32_t)p->arrays.size() : -1; }
+
+int64_t xeng_accumulator_bytes(int32_t n_inputs, int32_t n_chans) {
+  if (n_inputs < 1 || n_chans < 1) return -1;
+  return (int64_t)n_chans * nbl_of(n_inputs) * 2 * (int64_t)sizeof(int32_t);
 }
 
 int xeng_plan(xeng_plan_t** out, const xeng_array_desc* arrays, int32_t n_arrays, uint32_t flags,
               void* hip_stream) {
-  if (!out || !arrays || n_arrays < 1 || flags != 0) return XENG_EINVAL;
+  if (!out || n_arrays < 0 || (n_arrays > 0 && !arrays) || (flags & ~(uint32_t)XENG_PLAN_BATCH))
+    return XENG_EINVAL;
+  if (n_arrays == 0 && !(flags & XENG_PLAN_BATCH)) return XENG_EINVAL;
   *out = nullptr;
-  for (int32_t a = 0; a < n_arrays; ++a) {
-    const xeng_array_desc& d = arrays[a];
-    if (d.n_inputs < 1 || d.n_inputs > XENG_MAX_INPUTS || d.n_chans < 1 ||
-        d.max_time_per_call < 1 || d.max_time_per_call > XENG_MAX_INTEGRATION)
-      return XENG_EINVAL;
-  }
+  for (int32_t a = 0; a < n_arrays; ++a)
+    if (!valid_desc(arrays[a])) return XENG_EINVAL;
   xeng_plan_t* p = new (std::nothrow) xeng_plan_t();
   if (!p) return XENG_ENOMEM;
+  p->batched = n_arrays > 1 || (flags & XENG_PLAN_BATCH);
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
@@ -144,62 +400,152 @@ int xeng_plan(xeng_plan_t** out, const xeng_array_desc* arrays, int32_t n_arrays
     }
     p->own_stream = true;
   }
-  p->arrays.resize(n_arrays);
-  for (int32_t a = 0; a < n_arrays; ++a) {
-    ArrayState& s = p->arrays[a];
-    s.d = arrays[a];
-    const int nt = (s.d.n_inputs + 15) / 16;
-    s.k = (s.d.n_inputs % 16 == 0) ? xeng::x32_kernel(s.d.n_inputs) : xeng::stage_kernel(nt);
-    s.acc_bytes = (size_t)s.d.n_chans * nbl_of(s.d.n_inputs) * 2 * sizeof(int32_t);
-    e = hipMalloc(&s.acc, s.acc_bytes);
+  if (p->batched) {
+    const size_t cbytes = (xeng::batch::QUEUES + 1) * sizeof(int32_t);
+    e = hipMalloc(&p->counters, cbytes);
+    if (e == hipSuccess) e = hipMemsetAsync(p->counters, 0, cbytes, p->stream);
     if (e != hipSuccess) {
       xeng_destroy(p);
       return e == hipErrorOutOfMemory ? XENG_ENOMEM : XENG_EDEVICE;
     }
-    e = hipMemsetAsync(s.acc, 0, s.acc_bytes, p->stream);
-    if (e != hipSuccess) {
+  }
+  p->arrays.resize(n_arrays);
+  for (int32_t a = 0; a < n_arrays; ++a) {
+    const int st = init_slot(p, p->arrays[a], arrays[a]);
+    if (st != XENG_OK) {
       xeng_destroy(p);
-      return XENG_EDEVICE;
+      return st;
     }
   }
   *out = p;
   return XENG_OK;
 }
 
+int xeng_attach(xeng_plan_t* p, const xeng_array_desc* d, int32_t* index) {
+  if (!p || !d || !index) return XENG_EINVAL;
+  if (p->dead) return XENG_ESTATE;
+  if (!p->batched) return fail(p, XENG_EINVAL, "attach needs a batched plan");
+  if (!valid_desc(*d)) return fail(p, XENG_EINVAL, "bad array descriptor");
+  int32_t slot = 0;
+  while (slot < (int32_t)p->arrays.size() && p->arrays[slot].active) ++slot;
+  if (slot == (int32_t)p->arrays.size()) p->arrays.emplace_back();
+  const int st = init_slot(p, p->arrays[slot], *d);
+  if (st != XENG_OK) {
+    if (p->arrays[slot].acc) (void)hipFree(p->arrays[slot].acc);
+    p->arrays[slot] = ArrayState{};
+    return st;
+  }
+  *index = slot;
+  return XENG_OK;
+}
+
+int xeng_detach(xeng_plan_t* p, int32_t index) {
+  if (!p) return XENG_EINVAL;
+  if (p->dead) return XENG_ESTATE;
+  if (index < 0 || index >= (int32_t)p->arrays.size() || !p->arrays[index].active)
+    return fail(p, XENG_EINVAL, "slot %d holds no array", index);
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "detach synchronize");
+  e = hipFree(p->arrays[index].acc);
+  p->arrays[index] = ArrayState{};
+  if (e != hipSuccess) return hip_fail(p, e, "accumulator free");
+  return XENG_OK;
+}
+
 int xeng_correlate(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_t* n_time) {
   if (!p || !n_time) return XENG_EINVAL;
   if (p->dead) return XENG_ESTATE;
-  const int32_t na = (int32_t)p->arrays.size();
-  for (int32_t a = 0; a < na; ++a) {
-    const ArrayState& s = p->arrays[a];
-    const int64_t T = n_time[a];
-    if (T < 0 || T > s.d.max_time_per_call)
-      return fail(p, XENG_EINVAL, "array %d: n_time %lld outside [0, %lld]", a, (long long)T,
-                  (long long)s.d.max_time_per_call);
-    if (T > 0 && (!d_voltages || !d_voltages[a] || !aligned16(d_voltages[a])))
-      return fail(p, XENG_EINVAL, "array %d: voltage pointer null or not 16-byte aligned", a);
-    if (s.n_integrated + T > XENG_MAX_INTEGRATION)
-      return fail(p, XENG_EOVERFLOW, "array %d: %lld + %lld samples exceed %lld", a,
-                  (long long)s.n_integrated, (long long)T, (long long)XENG_MAX_INTEGRATION);
+  const int st = validate_call(p, d_voltages, n_time);
+  if (st != XENG_OK) return st;
+  return correlate_unchecked(p, d_voltages, n_time);
+}
+
+int xeng_autotune(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_t* n_time,
+                  int32_t reps, float* best_ms) {
+  if (!p || !n_time || reps < 1) return XENG_EINVAL;
+  if (p->dead) return XENG_ESTATE;
+  for (const ArrayState& s : p->arrays)
+    if (s.active && s.n_integrated != 0)
+      return fail(p, XENG_EINVAL, "autotune needs every accumulator freshly dumped");
+  int st = validate_call(p, d_voltages, n_time);
+  if (st != XENG_OK) return st;
+
+  hipEvent_t t0, t1;
+  if (hipEventCreate(&t0) != hipSuccess) return fail(p, XENG_EDEVICE, "event");
+  if (hipEventCreate(&t1) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return fail(p, XENG_EDEVICE, "event");
   }
-  for (int32_t a = 0; a < na; ++a) {
-    ArrayState& s = p->arrays[a];
-    const int64_t T = n_time[a];
-    if (T == 0) continue;
-    xeng::Args args{};
-    args.v = d_voltages[a];
-    args.acc = s.acc;
-    args.T = T;
-    args.F = s.d.n_chans;
-    args.N = s.d.n_inputs;
-    dim3 grid;
-    grid_for(p, s, T, grid, args.t_chunk, args.mode);
-    hipError_t e = s.k->launch(grid, p->stream, args);
-    if (e != hipSuccess) return hip_fail(p, e, "kernel launch");
-    s.n_integrated += T;
-    s.clean = false;
+  // one trial: reps calls from clean accumulators, timed on the stream
+  auto trial = [&](float& ms) -> int {
+    int r = zero_accumulators(p);
+    if (r != XENG_OK) return r;
+    r = correlate_unchecked(p, d_voltages, n_time);  // warm-up (also builds the graph)
+    if (r != XENG_OK) return r;
+    if (hipEventRecord(t0, p->stream) != hipSuccess) return fail(p, XENG_EDEVICE, "event record");
+    // (the sums of these calls are thrown away, so the overflow guard is not applied)
+    for (int i = 0; i < reps && r == XENG_OK; ++i) r = correlate_unchecked(p, d_voltages, n_time);
+    if (r != XENG_OK) return r;
+    if (hipEventRecord(t1, p->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess)
+      return fail(p, XENG_EDEVICE, "event wait");
+    return hipEventElapsedTime(&ms, t0, t1) == hipSuccess ? XENG_OK : fail(p, XENG_EDEVICE, "timing");
+  };
+
+  float best = 0;
+  if (p->batched) {
+    // work-item granularity of the persistent launch
+    const int cand[] = {1, 2, 4, 8};
+    int pick = p->batch_split;
+    for (int i = 0; i < 4 && st == XENG_OK; ++i) {
+      p->batch_split = cand[i];
+      float ms = 0;
+      st = trial(ms);
+      if (st == XENG_OK && (best == 0 || ms < best)) {
+        best = ms;
+        pick = cand[i];
+      }
+    }
+    p->batch_split = pick;
+  } else {
+    // per array: tile shape (32-row tiles of the ring kernel or 16-row tiles
+    // of the staging kernel) and workgroups per CU of the time split
+    for (ArrayState& s : p->arrays) {
+      if (!s.active) continue;
+      std::vector<const KernelInfo*> kernels;
+      if (s.d.n_inputs % 16 == 0) kernels.push_back(xeng::x32_kernel(s.d.n_inputs));
+      kernels.push_back(xeng::stage_kernel((s.d.n_inputs + 15) / 16));
+      const KernelInfo* pick_k = s.k;
+      int pick_split = s.split;
+      float arr_best = 0;
+      for (const KernelInfo* k : kernels) {
+        if (!k) continue;
+        for (int split : {1, 2, 4}) {
+          s.k = k;
+          s.split = split;
+          float ms = 0;
+          st = trial(ms);
+          if (st != XENG_OK) break;
+          if (arr_best == 0 || ms < arr_best) {
+            arr_best = ms;
+            pick_k = k;
+            pick_split = split;
+          }
+        }
+        if (st != XENG_OK) break;
+      }
+      s.k = pick_k;
+      s.split = pick_split;
+      best += arr_best;
+      if (st != XENG_OK) break;
+    }
   }
-  return XENG_OK;
+  const int z = zero_accumulators(p);
+  if (st == XENG_OK) st = z;
+  if (st == XENG_OK && hipStreamSynchronize(p->stream) != hipSuccess) st = fail(p, XENG_EDEVICE, "sync");
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st == XENG_OK && best_ms) *best_ms = best / (float)reps;
+  return st;
 }
 
 int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags,
@@ -209,24 +555,55 @@ int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags
   if (flags & ~(uint32_t)(XENG_DUMP_KEEP | XENG_DUMP_TO_HOST)) return XENG_EINVAL;
   const int32_t na = (int32_t)p->arrays.size();
   if (array < -1 || array >= na) return fail(p, XENG_EINVAL, "array index %d out of range", array);
+  if (array >= 0 && !p->arrays[array].active) return fail(p, XENG_EINVAL, "slot %d holds no array", array);
   const int32_t a0 = array < 0 ? 0 : array, a1 = array < 0 ? na : array + 1;
   for (int32_t a = a0; a < a1; ++a)
-    if (!dst[a - a0]) return fail(p, XENG_EINVAL, "dump destination %d is null", a - a0);
+    if (p->arrays[a].active && !dst[a - a0])
+      return fail(p, XENG_EINVAL, "dump destination %d is null", a - a0);
   const bool to_host = (flags & XENG_DUMP_TO_HOST) != 0;
+  const bool keep = (flags & XENG_DUMP_KEEP) != 0;
+  xeng::DumpParams dp{};
+  dp.clear = keep ? 0 : 1;
+  int64_t most = 0;
+  auto flush = [&]() -> int {
+    if (dp.count == 0) return XENG_OK;
+    const int64_t blocks = std::min<int64_t>((most + 1023) / 1024, 8LL * p->n_cu);
+    hipError_t e = xeng::dump_launch((int)std::max<int64_t>(1, blocks), p->stream, dp);
+    dp.count = 0;
+    most = 0;
+    return e == hipSuccess ? XENG_OK : hip_fail(p, e, "dump kernel");
+  };
   for (int32_t a = a0; a < a1; ++a) {
     ArrayState& s = p->arrays[a];
-    hipError_t e = hipMemcpyAsync(dst[a - a0], s.acc, s.acc_bytes,
-                                  to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                                  p->stream);
-    if (e != hipSuccess) return hip_fail(p, e, "dump copy");
+    if (!s.active) continue;
+    int32_t* d = dst[a - a0];
+    if (!to_host && (reinterpret_cast<uintptr_t>(d) & 7u) == 0) {
+      // device destination: one dump kernel copies (and clears) every array
+      dp.acc[dp.count] = reinterpret_cast<int2*>(s.acc);
+      dp.dst[dp.count] = reinterpret_cast<int2*>(d);
+      dp.n[dp.count] = (int64_t)(s.acc_bytes / sizeof(int2));
+      most = std::max(most, dp.n[dp.count]);
+      if (++dp.count == xeng::DUMP_MAX) {
+        const int st = flush();
+        if (st != XENG_OK) return st;
+      }
+    } else {
+      hipError_t e = hipMemcpyAsync(d, s.acc, s.acc_bytes,
+                                    to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, p->stream);
+      if (e != hipSuccess) return hip_fail(p, e, "dump copy");
+      if (!keep) {
+        e = hipMemsetAsync(s.acc, 0, s.acc_bytes, p->stream);
+        if (e != hipSuccess) return hip_fail(p, e, "dump clear");
+      }
+    }
     if (n_integrated) n_integrated[a - a0] = s.n_integrated;
-    if (!(flags & XENG_DUMP_KEEP)) {
-      e = hipMemsetAsync(s.acc, 0, s.acc_bytes, p->stream);
-      if (e != hipSuccess) return hip_fail(p, e, "dump clear");
+    if (!keep) {
       s.n_integrated = 0;
       s.clean = true;
     }
   }
+  const int st = flush();
+  if (st != XENG_OK) return st;
   if (to_host) {
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "dump synchronize");
@@ -237,8 +614,13 @@ int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags
 void xeng_destroy(xeng_plan_t* p) {
   if (!p) return;
   if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (int i = 0; i < xeng_plan_s::GRAPH_RING; ++i) {
+    if (p->exec[i]) (void)hipGraphExecDestroy(p->exec[i]);
+    if (p->done[i]) (void)hipEventDestroy(p->done[i]);
+  }
   for (ArrayState& s : p->arrays)
     if (s.acc) (void)hipFree(s.acc);
+  if (p->counters) (void)hipFree(p->counters);
   if (p->own_stream && p->stream) (void)hipStreamDestroy(p->stream);
   delete p;
 }

@@ -23,6 +23,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 XENG_OK, XENG_EINVAL, XENG_ENOMEM, XENG_EOVERFLOW, XENG_EDEVICE, XENG_ESTATE = 0, -1, -2, -3, -4, -5
 XENG_DUMP_KEEP = 1 << 0
 XENG_DUMP_TO_HOST = 1 << 1
+XENG_PLAN_BATCH = 1 << 0
 XENG_MAX_INPUTS = 256
 XENG_MAX_INTEGRATION = 16_777_215
 
@@ -53,6 +54,17 @@ _lib.xeng_last_error.argtypes = [_P]
 _lib.xeng_last_error.restype = ctypes.c_char_p
 _lib.xeng_integrated.argtypes = [_P, ctypes.c_int32]
 _lib.xeng_integrated.restype = ctypes.c_int64
+_lib.xeng_attach.argtypes = [_P, ctypes.POINTER(xeng_array_desc), ctypes.POINTER(ctypes.c_int32)]
+_lib.xeng_attach.restype = ctypes.c_int
+_lib.xeng_detach.argtypes = [_P, ctypes.c_int32]
+_lib.xeng_detach.restype = ctypes.c_int
+_lib.xeng_slots.argtypes = [_P]
+_lib.xeng_slots.restype = ctypes.c_int32
+_lib.xeng_accumulator_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.xeng_accumulator_bytes.restype = ctypes.c_int64
+_lib.xeng_autotune.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_float)]
+_lib.xeng_autotune.restype = ctypes.c_int
 
 
 class XengError(RuntimeError):
@@ -111,6 +123,34 @@ def xeng_destroy(plan: int) -> None:
     _lib.xeng_destroy(plan)
 
 
+def xeng_attach(plan: int, n_inputs: int, n_chans: int, max_time_per_call: int) -> int:
+    d = xeng_array_desc(n_inputs, n_chans, max_time_per_call)
+    idx = ctypes.c_int32()
+    _check(_lib.xeng_attach(plan, ctypes.byref(d), ctypes.byref(idx)), plan)
+    return idx.value
+
+
+def xeng_detach(plan: int, index: int) -> None:
+    _check(_lib.xeng_detach(plan, index), plan)
+
+
+def xeng_slots(plan: int) -> int:
+    return int(_lib.xeng_slots(plan))
+
+
+def xeng_accumulator_bytes(n_inputs: int, n_chans: int) -> int:
+    return int(_lib.xeng_accumulator_bytes(n_inputs, n_chans))
+
+
+def xeng_autotune(plan: int, voltages: Sequence, n_time: Sequence[int], reps: int = 3) -> float:
+    n = len(n_time)
+    ptrs = (_P * n)(*[_ptr(v) for v in voltages])
+    ts = (ctypes.c_int64 * n)(*n_time)
+    best = ctypes.c_float()
+    _check(_lib.xeng_autotune(plan, ptrs, ts, reps, ctypes.byref(best)), plan)
+    return best.value
+
+
 def xeng_nbaselines(n: int) -> int:
     return int(_lib.xeng_nbaselines(n))
 
@@ -144,18 +184,24 @@ class ArraySpec:
 
 
 class Plan:
-    """Owns one C plan; checks tensor shapes/dtypes before handing pointers over."""
+    """Owns one C plan; checks tensor shapes/dtypes before handing pointers over.
 
-    def __init__(self, arrays: Sequence[tuple[int, int, int]], stream=None):
+    Array slots are indexed as in the C ABI; ``specs[k]`` is None for a free
+    slot of a batched plan (after ``detach``)."""
+
+    def __init__(self, arrays: Sequence[tuple[int, int, int]], stream=None, batch: bool = False):
         """stream: a torch.cuda.Stream the engine runs on; by default a new one.
+        batch: force the batched form (persistent graph launch) even for one or
+        zero arrays; it is implied by more than one array.
         correlate() orders the engine after the caller's current stream, and
         dump() orders the caller's current stream after the engine."""
         import torch
-        self.specs = [ArraySpec(*a) for a in arrays]
+        self.specs: list[ArraySpec | None] = [ArraySpec(*a) for a in arrays]
         self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.batched = batch or len(self.specs) > 1
         self.handle = None
         self.handle = xeng_plan([(s.n_inputs, s.n_chans, s.max_time_per_call) for s in self.specs],
-                                0, self.stream.cuda_stream)
+                                XENG_PLAN_BATCH if batch else 0, self.stream.cuda_stream)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -170,26 +216,58 @@ class Plan:
     def __exit__(self, *exc):
         self.close()
 
-    def correlate(self, voltages) -> None:
-        """voltages: one uint8 CUDA tensor [T, F, N] per array (None skips)."""
+    def attach(self, n_inputs: int, n_chans: int, max_time_per_call: int) -> int:
+        """Admit one more array (batched plans); returns its slot."""
+        idx = xeng_attach(self.handle, n_inputs, n_chans, max_time_per_call)
+        spec = ArraySpec(n_inputs, n_chans, max_time_per_call)
+        if idx == len(self.specs):
+            self.specs.append(spec)
+        else:
+            self.specs[idx] = spec
+        return idx
+
+    def detach(self, index: int) -> None:
+        """Free a slot and its accumulator (waits for the engine's stream)."""
+        xeng_detach(self.handle, index)
+        self.specs[index] = None
+
+    def _marshal(self, voltages):
         import torch
         if len(voltages) != len(self.specs):
-            raise ValueError("one voltage tensor (or None) per array")
+            raise ValueError("one voltage tensor (or None) per slot")
         ptrs, ts = [], []
-        self.stream.wait_stream(torch.cuda.current_stream())
         for v, s in zip(voltages, self.specs):
             if v is None:
                 ptrs.append(None)
                 ts.append(0)
                 continue
+            if s is None:
+                raise ValueError("voltages given for a free slot")
             if v.dtype != torch.uint8 or not v.is_cuda or not v.is_contiguous():
                 raise ValueError("voltages must be contiguous uint8 device tensors")
             if v.dim() != 3 or v.shape[1] != s.n_chans or v.shape[2] != s.n_inputs:
                 raise ValueError(f"voltage block {tuple(v.shape)} does not match [T, {s.n_chans}, {s.n_inputs}]")
             ptrs.append(v)
             ts.append(v.shape[0])
-            v.record_stream(self.stream)
+        return ptrs, ts
+
+    def correlate(self, voltages) -> None:
+        """voltages: one uint8 CUDA tensor [T, F, N] per slot (None skips)."""
+        import torch
+        ptrs, ts = self._marshal(voltages)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        for v in ptrs:
+            if v is not None:
+                v.record_stream(self.stream)
         xeng_correlate(self.handle, ptrs, ts)
+
+    def autotune(self, voltages, reps: int = 3) -> float:
+        """Pick launch shapes by timing them on these inputs (accumulators must
+        be freshly dumped; they are zero afterwards).  Returns ms per call."""
+        import torch
+        ptrs, ts = self._marshal(voltages)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        return xeng_autotune(self.handle, ptrs, ts, reps)
 
     def new_output(self, array: int, host: bool = False):
         import torch
@@ -198,11 +276,12 @@ class Plan:
                            device="cpu" if host else "cuda", pin_memory=host)
 
     def dump(self, array: int = -1, out=None, keep: bool = False, to_host: bool = False):
-        """Returns (list of int32 [F, nbl, 2] tensors, list of n_integrated)."""
+        """Returns (list of int32 [F, nbl, 2] tensors, list of n_integrated);
+        with array = -1 one entry per slot (None for a free slot)."""
         import torch
         idx = list(range(len(self.specs))) if array < 0 else [array]
         if out is None:
-            out = [self.new_output(a, host=to_host) for a in idx]
+            out = [None if self.specs[a] is None else self.new_output(a, host=to_host) for a in idx]
         self.stream.wait_stream(torch.cuda.current_stream())   # out may come from the caller's stream
         flags = (XENG_DUMP_KEEP if keep else 0) | (XENG_DUMP_TO_HOST if to_host else 0)
         n = xeng_dump(self.handle, array, out, flags)

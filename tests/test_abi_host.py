@@ -59,3 +59,29 @@ def test_null_arguments():
     assert lib.xeng_dump(None, 0, None, 0, None) == X.XENG_EINVAL
     lib.xeng_destroy(None)
     assert X.xeng_integrated(None, 0) == -1
+
+
+def test_null_arguments_of_batch_and_serving_calls():
+    from paper_1904_07778_amd import xeng as X
+    lib = X._lib
+    assert lib.xeng_attach(None, None, None) == X.XENG_EINVAL
+    assert lib.xeng_detach(None, 0) == X.XENG_EINVAL
+    assert lib.xeng_autotune(None, None, None, 1, None) == X.XENG_EINVAL
+    assert X.xeng_slots(None) == -1
+
+
+def test_accumulator_bytes():
+    from paper_1904_07778_amd import xeng as X
+    assert X.xeng_accumulator_bytes(192, 1024) == 1024 * 18528 * 8
+    assert X.xeng_accumulator_bytes(1, 1) == 8
+    assert X.xeng_accumulator_bytes(0, 5) == -1 and X.xeng_accumulator_bytes(5, 0) == -1
+
+
+def test_plan_flags_and_empty_plans():
+    from paper_1904_07778_amd import xeng as X
+    with pytest.raises(X.XengError) as e:
+        X.xeng_plan([])                       # an empty plan must be a batched one
+    assert e.value.status == X.XENG_EINVAL
+    with pytest.raises(X.XengError) as e:
+        X.xeng_plan([(8, 4, 10)], flags=1 << 5)   # unknown flag
+    assert e.value.status == X.XENG_EINVAL
