@@ -17,6 +17,19 @@ all channels), the roofline of the dominant kernel (timed live with HIP
 events on the engine's stream) and the CPU oracle timed on a bounded sample
 of the same workload.
 
+Other workloads (one JSON line each, same keys plus a comparison):
+  --workload batch    12 arrays of uneven N, F, T (seeded): one batched call
+                      (persistent launch in a captured graph) + one dump per
+                      step, against 12 plain correlate + dump calls on the
+                      same stream; both autotuned first; outputs compared
+                      bit for bit.
+  --workload stream   four sub-arrays (N=192/96/32/32, F=1024/1024/1024/256)
+                      in two waves under a memory budget that makes the
+                      second wave wait: saturating throughput of the serving
+                      loop against a plain loop (one launch per block per
+                      sub-array), then a paced run at the 250 MSPS block rate
+                      for dump latency p50/p99.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
        python bench.py --copy-calibration   (plain device copy of known size,
                                              for scaling HBM byte counters)
@@ -107,7 +120,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "dish", "dish_tiny"])
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "dish", "dish_tiny", "batch", "stream"])
+    ap.add_argument("--stream-dumps", type=int, default=4, help="dumps per request (stream, saturating)")
+    ap.add_argument("--paced-seconds", type=float, default=6.0, help="length of the paced run (stream)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -132,6 +147,11 @@ def main() -> int:
     if args.copy_calibration:
         copy_calibration()
         return 0
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "stream":
+        return bench_stream(args)
 
     w = synth.WORKLOADS[args.workload]
     N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
@@ -209,6 +229,197 @@ def main() -> int:
     }
     print(json.dumps(rec), flush=True)
     plan.close()
+    return 0
+
+
+def _base_record(args, metric, value, ms_per_step, config):
+    return {"metric": metric, "value": value, "unit": "CMAC/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int8", "data": "synthetic",
+            "config": config}
+
+
+def bench_batch(args) -> int:
+    """Batched workload: one batched call vs 12 plain calls per step."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1904_07778_amd.xeng import Plan
+
+    specs = synth.batch_arrays()
+    shapes = [(s["n_inputs"], s["n_chans"], s["n_time"]) for s in specs]
+    log(f"batch workload: {shapes}")
+    dev = [torch.from_numpy(synth.voltages("noise", 4, n, f, t, array=k)).cuda()
+           for k, (n, f, t) in enumerate(shapes)]
+    cmac = sum(n * (n + 1) // 2 * f * t for n, f, t in shapes)
+    in_bytes = sum(n * f * t for n, f, t in shapes)
+    out_bytes = sum(n * (n + 1) // 2 * f * 8 for n, f, t in shapes)
+    stream = torch.cuda.Stream()
+    batched = Plan(shapes, stream=stream)
+    plain = [Plan([sh], stream=stream) for sh in shapes]
+    torch.cuda.synchronize()
+    log("autotuning")
+    tb = batched.autotune(dev, reps=3)
+    tp = sum(p.autotune([v], reps=3) for p, v in zip(plain, dev))
+    log(f"autotuned: batched {tb:.3f} ms, plain sum {tp:.3f} ms")
+    out_b = [batched.new_output(k) for k in range(len(shapes))]
+    out_p = [p.new_output(0) for p in plain]
+
+    def step_batched():
+        batched.correlate(dev)
+        batched.dump(-1, out=out_b)
+
+    def step_plain():
+        for p, v, o in zip(plain, dev, out_p):
+            p.correlate([v])
+            p.dump(0, out=[o])
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / args.steps, e0.elapsed_time(e1) / args.steps
+
+    ms_b, dev_ms_b = timed(step_batched)
+    ms_p, dev_ms_p = timed(step_plain)
+    same = all(torch.equal(a, b) for a, b in zip(out_b, out_p))
+    log(f"batched {ms_b:.3f} ms/step, plain {ms_p:.3f} ms/step, identical={same}")
+    rec = _base_record(args, "X-engine complex MAC/s, 12 arrays in one batched call (correlate + dump)",
+                       cmac / (ms_b / 1e3), ms_b,
+                       {"workload": "batch: 12 arrays, N in {16..192}, F in {256, 512, 1024}, "
+                                    "T in {2048, 4096, 8192} (seed 4), 4+4-bit complex",
+                        "arrays": shapes, "step": "batched correlate + dump of all arrays"})
+    rec.update({
+        "plain_value": cmac / (ms_p / 1e3), "plain_ms_per_step": ms_p,
+        "speedup_vs_plain": ms_p / ms_b, "identical_to_plain": same,
+        "device_ms_per_step": dev_ms_b, "plain_device_ms_per_step": dev_ms_p,
+        "autotuned_ms": {"batched": tb, "plain_sum": tp},
+        "int8_mfma_frac_of_step": cmac * OPS_PER_CMAC / (ms_b / 1e3) / (PEAK_INT8_TOPS * 1e12),
+        "roofline": {"bound": "hbm", "achieved": (in_bytes + out_bytes) / (dev_ms_b / 1e3) / 1e9,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": (in_bytes + out_bytes) / (dev_ms_b / 1e3) / 1e9 / PEAK_HBM_GBS,
+                     "traffic": None, "algorithmic_bytes": in_bytes + out_bytes,
+                     "note": "whole step (batch kernel + dump kernel) on the engine stream"},
+        "cpu_baseline": None,
+    })
+    print(json.dumps(rec), flush=True)
+    batched.close()
+    for p in plain:
+        p.close()
+    return 0 if same else 1
+
+
+def bench_stream(args) -> int:
+    """Streaming workload: serving loop vs plain per-block launches."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1904_07778_amd.serve import (BLOCK_T, Feed, Request, Server, drive, latency_stats,
+                                            realtime_period)
+    from paper_1904_07778_amd.xeng import Plan
+
+    subs = synth.stream_subarrays()
+    ring_blocks = 4
+    log(f"stream workload: {subs}")
+    rings = {}
+    for k, s in enumerate(subs):
+        n, f = s["n_inputs"], s["n_chans"]
+        rings[(n, f)] = torch.from_numpy(synth.voltages("sources", 5, n, f, ring_blocks * BLOCK_T,
+                                                        array=k, n_src=1)).cuda()
+
+    def requests(n_dumps_of, waves=2):
+        reqs = []
+        for w in range(waves):
+            for s in subs:
+                reqs.append(Request(f"{s['n_inputs']}x{s['n_chans']}#{w}", s["n_inputs"], s["n_chans"],
+                                    s["dump_len"], n_dumps_of(s), ring_blocks=ring_blocks))
+        return reqs
+
+    def feeds_for(reqs):
+        return {r.name: Feed(rings[(r.n_inputs, r.n_chans)], r.n_dumps * r.dump_len // BLOCK_T)
+                for r in reqs}
+
+    fps = [r.footprint() for r in requests(lambda s: 1, waves=1)]
+    budget = sum(fps)            # one wave fits; the second waits for memory
+    real_need = sum(s["n_inputs"] * (s["n_inputs"] + 1) // 2 * REALTIME_SPECTRA_PER_S for s in subs)
+
+    # saturating: the serving loop
+    reqs = requests(lambda s: args.stream_dumps)
+    cmac = sum(r.n_inputs * (r.n_inputs + 1) // 2 * r.n_chans * r.n_dumps * r.dump_len for r in reqs)
+    drive(Server(budget, keep_results=False), [(0.0, r) for r in requests(lambda s: 1)],
+          feeds_for(requests(lambda s: 1)), paced=False)        # warm-up (graphs, allocator)
+    srv = Server(budget, keep_results=False)
+    t_serve = drive(srv, [(0.0, r) for r in reqs], feeds_for(reqs), paced=False)
+    srv.close()
+    log(f"serving loop: {t_serve:.3f} s for {cmac:.3e} CMAC, {srv.iterations} engine calls")
+
+    # saturating: plain loop, one launch per block per sub-array, round robin
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    for _wave in range(2):
+        active = []
+        for s in subs:
+            p = Plan([(s["n_inputs"], s["n_chans"], BLOCK_T)], stream=stream)
+            out = p.new_output(0)
+            active.append({"s": s, "plan": p, "done": 0, "out": out,
+                           "host": torch.empty(out.shape, dtype=out.dtype, pin_memory=True),
+                           "blocks": args.stream_dumps * s["dump_len"] // BLOCK_T})
+        while active:
+            for a in list(active):
+                s, p = a["s"], a["plan"]
+                ring = rings[(s["n_inputs"], s["n_chans"])]
+                row = (a["done"] % ring_blocks) * BLOCK_T
+                p.correlate([ring[row: row + BLOCK_T]])
+                a["done"] += 1
+                if a["done"] * BLOCK_T % s["dump_len"] == 0:
+                    p.dump(0, out=[a["out"]])
+                    a["host"].copy_(a["out"], non_blocking=True)
+                if a["done"] == a["blocks"]:
+                    torch.cuda.synchronize()
+                    p.close()
+                    active.remove(a)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    log(f"plain loop: {t_plain:.3f} s")
+
+    # paced: blocks at the real-time rate, latency of every dump
+    def paced_dumps(s):
+        return max(1, int(round(args.paced_seconds / (s["dump_len"] / BLOCK_T * realtime_period(s["n_chans"])))))
+    preqs = requests(paced_dumps, waves=1)
+    psrv = Server(budget, keep_results=False)
+    t_paced = drive(psrv, [(0.0, r) for r in preqs], feeds_for(preqs), paced=True,
+                    time_limit=4 * args.paced_seconds + 60)
+    psrv.close()
+    lat = latency_stats(psrv.done)
+    per = {r.name: latency_stats([d for d in psrv.done if d.name == r.name]) for r in preqs}
+    log(f"paced: {t_paced:.2f} s, {lat}")
+
+    value = cmac / t_serve
+    rec = _base_record(args, "X-engine complex MAC/s of the streaming serving loop (saturating)",
+                       value, 1e3 * t_serve / max(1, srv.iterations),
+                       {"workload": "stream: sub-arrays N/F = 192/1024, 96/1024, 32/1024, 32/256, "
+                                    "blocks of 1024 samples, dump lengths "
+                                    + "/".join(str(s["dump_len"]) for s in subs)
+                                    + f", two waves of {args.stream_dumps} dumps each under a "
+                                      "budget that fits one wave; blocks pre-staged in HBM rings",
+                        "budget_bytes": budget})
+    rec["steps"] = srv.iterations
+    rec.update({
+        "plain_value": cmac / t_plain, "speedup_vs_plain": t_plain / t_serve,
+        "rtf": value / real_need,
+        "paced": {"seconds": t_paced, **lat, "per_subarray": per},
+        "roofline": None, "cpu_baseline": None,
+    })
+    print(json.dumps(rec), flush=True)
     return 0
 
 
