@@ -152,6 +152,17 @@ __device__ __forceinline__ int xcd_group(int b, int groups) {
   return x * q + (x < r ? x : r) + k;
 }
 
+// Wait states between the last MFMAs and the epilogue, whose accumulator
+// reads are inline asm (v_accvgpr_read) and so not covered by the compiler's
+// hazard handling: a VALU read of a 16-pass MFMA result needs 19 (an 8-pass
+// one 11); this gives 32.  Without it the first reads of the last-written
+// tiles can see values from before the final MFMA.
+__device__ __forceinline__ void mfma_drain() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 struct Args {
   const uint8_t* v;  // [T][F][N]
   int32_t* acc;      // [F][nbl][2]
@@ -324,6 +335,7 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds) {
     if (more) store_step(buf ^ 1);
     __syncthreads();
   }
+  mfma_drain();
 
   const int f = f0 + c;
   if (f >= a.F) return;

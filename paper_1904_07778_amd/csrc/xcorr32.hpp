@@ -168,6 +168,7 @@ __device__ __forceinline__ v16i mfma32(v4i a, v4i b, v16i c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
+
 // Add one wave's tiles into the accumulator of channel f.  32x32 result
 // layout: lane l, register v hold row 8(v/4) + 4(l/32) + v%4, column l%32;
 // the 32 lanes of a half-wave write 32 consecutive baselines of one row.
@@ -384,6 +385,7 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   mfma_step(P0);
   interleave();
   mfma_step(P1);
+  mfma_drain();
 
   // ---- epilogue: publish each column's Im' diagonal through LDS, then add
   __syncthreads();  // the ring is no longer read
