@@ -121,11 +121,13 @@ int xeng_correlate(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64
  *                 slots are skipped and their pointer ignored), each int32
  *                 [F][N(N+1)/2][2]; device memory, or host memory with
  *                 XENG_DUMP_TO_HOST.  Caller-owned.  8-byte aligned device
- *                 destinations are written by one copy-and-clear kernel for
- *                 all dumped arrays; others by a copy and a memset.
+ *                 destinations are written by one copy kernel for all dumped
+ *                 arrays; others by a copy each.
  *   flags         XENG_DUMP_KEEP: do not reset; XENG_DUMP_TO_HOST: see above.
  *   n_integrated  optional out, one per dumped array: samples in the dump.
- * Without KEEP the accumulators are zeroed and the sample count reset.
+ * Without KEEP the integration restarts from zero and the sample count is
+ * reset (the accumulator memory is overwritten by the next launch, or
+ * cleared first when that launch adds atomically).
  * Stream-ordered after all earlier correlate calls; with TO_HOST it waits for
  * the copy before returning.  Errors: EINVAL, EDEVICE, ESTATE.
  */

@@ -1,6 +1,7 @@
-// Dump kernel: copy accumulators out and (unless kept) clear them, for any
-// number of arrays in one launch.  A kernel rather than a copy plus a memset:
-// one launch for all arrays, and it may be recorded into a captured graph.
+// Dump kernel: copy accumulators out for any number of arrays in one launch
+// (a null source writes zeros: the same kernel clears accumulators).  A
+// kernel rather than copies and memsets: one launch for all arrays, and it
+// may be recorded into a captured graph.
 #include "kernels.hpp"
 
 namespace xeng {
@@ -9,13 +10,13 @@ namespace {
 __global__ __launch_bounds__(256) void dump_kernel(DumpParams d) {
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int k = 0; k < d.count; ++k) {
-    int2* __restrict__ acc = d.acc[k];
+    const int2* __restrict__ src = d.acc[k];
     int2* __restrict__ dst = d.dst[k];
     const int64_t n = d.n[k];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-      const int2 v = acc[i];
-      dst[i] = v;
-      if (d.clear) acc[i] = int2{0, 0};
+    if (src) {
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    } else {
+      for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) dst[i] = int2{0, 0};
     }
   }
 }

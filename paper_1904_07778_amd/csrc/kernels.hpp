@@ -31,15 +31,14 @@ inline const KernelInfo* x32_kernel(int n) {
   return k;
 }
 
-// Copy n[k] int2 values (re, im) from acc[k] to dst[k] for k < count, and
-// zero acc[k] when clear is set.  Pointers are 8-byte aligned device memory.
+// Copy n[k] int2 values (re, im) from acc[k] to dst[k] for k < count; a
+// null acc[k] writes zeros.  Pointers are 8-byte aligned device memory.
 constexpr int DUMP_MAX = 24;
 struct DumpParams {
-  int2* acc[DUMP_MAX];
+  const int2* acc[DUMP_MAX];
   int2* dst[DUMP_MAX];
   int64_t n[DUMP_MAX];
   int count;
-  int clear;
 };
 hipError_t dump_launch(int grid, hipStream_t s, const DumpParams& d);
 

@@ -34,7 +34,10 @@ struct ArrayState {
   int32_t* acc = nullptr;
   size_t acc_bytes = 0;
   int64_t n_integrated = 0;
-  bool clean = true;  // accumulator is all zero (no launch since the last clear)
+  bool clean = true;   // integration is empty (no launch since the last dump or clear)
+  bool zeroed = true;  // accumulator memory holds zeros (a dump does not clear it:
+                       // the next launch overwrites it with plain stores, or
+                       // zeroes it first when it must add atomically)
   const KernelInfo* k = nullptr;  // kernel of the plain launch
   int split = 2;                  // plain launch: aim for split * n_cu workgroups
 };
@@ -128,6 +131,33 @@ int init_slot(xeng_plan_t* p, ArrayState& s, const xeng_array_desc& d) {
   return XENG_OK;
 }
 
+// Zero the accumulators of the given arrays with one kernel launch (the dump
+// kernel with a null source), so the launch may be recorded into a graph.
+int zero_fill(xeng_plan_t* p, const std::vector<ArrayState*>& arrays) {
+  xeng::DumpParams dp{};
+  int64_t most = 0;
+  auto flush = [&]() -> int {
+    if (dp.count == 0) return XENG_OK;
+    const int64_t blocks = std::min<int64_t>((most + 1023) / 1024, 8LL * p->n_cu);
+    hipError_t e = xeng::dump_launch((int)std::max<int64_t>(1, blocks), p->stream, dp);
+    dp.count = 0;
+    most = 0;
+    return e == hipSuccess ? XENG_OK : hip_fail(p, e, "accumulator clear");
+  };
+  for (ArrayState* s : arrays) {
+    dp.acc[dp.count] = nullptr;
+    dp.dst[dp.count] = reinterpret_cast<int2*>(s->acc);
+    dp.n[dp.count] = (int64_t)(s->acc_bytes / sizeof(int2));
+    most = std::max(most, dp.n[dp.count]);
+    s->zeroed = true;
+    if (++dp.count == xeng::DUMP_MAX) {
+      const int st = flush();
+      if (st != XENG_OK) return st;
+    }
+  }
+  return flush();
+}
+
 xeng::Args base_args(const ArrayState& s, const uint8_t* v, int64_t T) {
   xeng::Args a{};
   a.v = v;
@@ -142,6 +172,10 @@ int launch_plain(xeng_plan_t* p, ArrayState& s, const uint8_t* v, int64_t T) {
   xeng::Args args = base_args(s, v, T);
   dim3 grid;
   grid_for(p, s, T, grid, args.t_chunk, args.mode);
+  if (args.mode == xeng::EPI_ATOMIC && s.clean && !s.zeroed) {
+    const int st = zero_fill(p, {&s});
+    if (st != XENG_OK) return st;
+  }
   hipError_t e = s.k->launch(grid, p->stream, args);
   return e == hipSuccess ? XENG_OK : hip_fail(p, e, "kernel launch");
 }
@@ -203,6 +237,16 @@ int record_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_tim
   }
   std::stable_sort(items.begin(), items.end(),
                    [](const BatchEntry& x, const BatchEntry& y) { return x.item_cycles > y.item_cycles; });
+  // arrays that start an integration with atomic adds need zeroed memory
+  std::vector<ArrayState*> to_zero;
+  for (const BatchEntry& b : items) {
+    ArrayState& s = p->arrays[b.a];
+    if (b.nchunks > 1 && s.clean && !s.zeroed) to_zero.push_back(&s);
+  }
+  if (!to_zero.empty()) {
+    const int st = zero_fill(p, to_zero);
+    if (st != XENG_OK) return st;
+  }
   for (size_t first = 0; first < items.size(); first += xeng::batch::MAX_ARRAYS) {
     xeng::batch::Params bp{};
     bp.counters = p->counters;
@@ -287,7 +331,7 @@ int zero_accumulators(xeng_plan_t* p) {
     if (!s.active) continue;
     hipError_t e = hipMemsetAsync(s.acc, 0, s.acc_bytes, p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "accumulator clear");
-    s.clean = true;
+    s.clean = s.zeroed = true;
     s.n_integrated = 0;
   }
   return XENG_OK;
@@ -328,7 +372,7 @@ int correlate_unchecked(xeng_plan_t* p, const uint8_t* const* d_voltages, const 
     ArrayState& s = p->arrays[a];
     if (!s.active || n_time[a] == 0) continue;
     s.n_integrated += n_time[a];
-    s.clean = false;
+    s.clean = s.zeroed = false;
   }
   return XENG_OK;
 }
@@ -562,8 +606,10 @@ int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags
       return fail(p, XENG_EINVAL, "dump destination %d is null", a - a0);
   const bool to_host = (flags & XENG_DUMP_TO_HOST) != 0;
   const bool keep = (flags & XENG_DUMP_KEEP) != 0;
+  // An empty integration whose memory still holds an earlier dump's sums
+  // (clean, not zeroed) is dumped as zeros.  Without KEEP the accumulator is
+  // not cleared here: it is marked empty, and the next launch overwrites it.
   xeng::DumpParams dp{};
-  dp.clear = keep ? 0 : 1;
   int64_t most = 0;
   auto flush = [&]() -> int {
     if (dp.count == 0) return XENG_OK;
@@ -577,9 +623,10 @@ int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags
     ArrayState& s = p->arrays[a];
     if (!s.active) continue;
     int32_t* d = dst[a - a0];
+    const bool stale = s.clean && !s.zeroed;
     if (!to_host && (reinterpret_cast<uintptr_t>(d) & 7u) == 0) {
-      // device destination: one dump kernel copies (and clears) every array
-      dp.acc[dp.count] = reinterpret_cast<int2*>(s.acc);
+      // device destination: one dump kernel copies every array
+      dp.acc[dp.count] = stale ? nullptr : reinterpret_cast<const int2*>(s.acc);
       dp.dst[dp.count] = reinterpret_cast<int2*>(d);
       dp.n[dp.count] = (int64_t)(s.acc_bytes / sizeof(int2));
       most = std::max(most, dp.n[dp.count]);
@@ -588,13 +635,13 @@ int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags
         if (st != XENG_OK) return st;
       }
     } else {
+      if (stale) {
+        const int st = zero_fill(p, {&s});
+        if (st != XENG_OK) return st;
+      }
       hipError_t e = hipMemcpyAsync(d, s.acc, s.acc_bytes,
                                     to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, p->stream);
       if (e != hipSuccess) return hip_fail(p, e, "dump copy");
-      if (!keep) {
-        e = hipMemsetAsync(s.acc, 0, s.acc_bytes, p->stream);
-        if (e != hipSuccess) return hip_fail(p, e, "dump clear");
-      }
     }
     if (n_integrated) n_integrated[a - a0] = s.n_integrated;
     if (!keep) {

@@ -176,7 +176,7 @@ def test_attach_detach_slots():
 
 def test_dump_kernel_and_copy_paths_agree():
     """Device dumps to 8-byte aligned buffers go through the dump kernel; a
-    misaligned destination falls back to a copy and a memset."""
+    misaligned destination falls back to a plain copy."""
     import torch
     from paper_1904_07778_amd.xeng import Plan
     rng = np.random.default_rng(23)
@@ -226,3 +226,24 @@ def test_full_batched_workload_sampled():
         want = oracle_vis([h], s["n_inputs"], s["n_chans"], chans=chans)
         got = batched[k][chans].cpu().numpy()
         assert np.array_equal(got, want), f"array {k}: " + first_mismatch(got, want)
+
+
+def test_batched_restart_after_dump_with_time_split():
+    """Batched call whose items split time (atomic adds) right after a dump
+    that left the old sums in memory."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    rng = np.random.default_rng(37)
+    shapes = [(192, 1, 20000), (48, 2, 20000), (40, 1, 20000)]
+    b1 = [rand_block(rng, 700, F, N) for N, F, _ in shapes]
+    b2 = [rand_block(rng, 20000, F, N) for N, F, _ in shapes]
+    print("batched restart after dump", flush=True)
+    with Plan(shapes) as p:
+        p.correlate([to_dev(b) for b in b1])
+        p.dump()
+        p.correlate([to_dev(b) for b in b2])
+        out, n = p.dump(to_host=True)
+    torch.cuda.synchronize()
+    for (N, F, _), b, got in zip(shapes, b2, out):
+        want = oracle_vis([b], N, F)
+        assert np.array_equal(got.numpy(), want), f"N={N}: " + first_mismatch(got.numpy(), want)

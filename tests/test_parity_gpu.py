@@ -160,3 +160,41 @@ def test_cylinder_scale_sampled_channels():
     # Eq. 3: RMS = sqrt(P / 2N) of every input on every channel lies in 2..3
     rms = np.sqrt(autos[..., 0] / (2 * T))
     assert 2.0 < rms.mean() < 3.0
+
+
+@pytest.mark.parametrize("to_host", [False, True])
+def test_restart_after_dump_every_epilogue(to_host):
+    """After a dump the integration restarts from zero whatever the next launch
+    does: plain stores (one workgroup per channel), atomic adds (time split
+    over workgroups) or read-modify-write (second call), and an empty
+    integration dumps as zeros; device and host destinations."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    rng = np.random.default_rng(31)
+    N, F = 192, 2
+    blocks = [synth.pack(rng.integers(-8, 8, size=(t, F, N)), rng.integers(-8, 8, size=(t, F, N)))
+              for t in (3000, 20000, 512, 700)]
+    print("restart after dump, to_host", to_host, flush=True)
+
+    def dump(p):
+        out, n = p.dump(to_host=to_host)
+        return (out[0] if to_host else out[0].cpu()).numpy(), n[0]
+
+    with Plan([(N, F, 20000)]) as p:
+        p.correlate([torch.from_numpy(blocks[0]).cuda()])        # plain stores
+        g0, _ = dump(p)
+        p.correlate([torch.from_numpy(blocks[1]).cuda()])        # time split: atomics on a dumped accumulator
+        g1, _ = dump(p)
+        g2, n2 = dump(p)                                         # empty integration
+        p.correlate([torch.from_numpy(blocks[2]).cuda()])        # plain stores
+        p.correlate([torch.from_numpy(blocks[3]).cuda()])        # read-modify-write
+        g3, n3 = dump(p)
+    torch.cuda.synchronize()
+    for got, bl in ((g0, [blocks[0]]), (g1, [blocks[1]]), (g3, blocks[2:])):
+        e = oracle.Engine(N, F)
+        for b in bl:
+            e.correlate(b)
+        want = e.dump()[0]
+        assert np.array_equal(got, want), first_mismatch(got, want)
+    assert n2 == 0 and not g2.any()
+    assert n3 == 1212
