@@ -172,3 +172,24 @@ def stream_subarrays(seed: int = 5):
     r = _rng(seed, (3,))
     dumps = r.choice([8192, 16384, 32768, 65536], size=len(shapes))
     return [dict(n_inputs=n, n_chans=f, dump_len=int(d)) for (n, f), d in zip(shapes, dumps)]
+
+
+def pfb_words(seed: int, n_inputs: int, n_chans: int, n_time: int, sigma: float = 2.0 ** 14) -> np.ndarray:
+    """F-engine output words, uint64 [T][F][N]: 18-bit two's-complement real
+    part in bits 35..18, imaginary part in bits 17..0 (fix_18_17 integers),
+    Gaussian with the given sigma, clipped to the 18-bit range; bits 36..63
+    carry seeded junk, which the equaliser ignores."""
+    r = _rng(seed, (4,))
+    z = r.normal(0.0, sigma, size=(n_time, n_chans, n_inputs, 2))
+    v = np.clip(np.rint(z), -(1 << 17), (1 << 17) - 1).astype(np.int64) & 0x3FFFF
+    junk = r.integers(0, 1 << 28, size=(n_time, n_chans, n_inputs), dtype=np.int64)
+    return ((junk << 36) | (v[..., 0] << 18) | v[..., 1]).astype(np.uint64)
+
+
+def eq_gains(seed: int, n_inputs: int, n_chans: int, center: float = 320.0, spread: float = 0.2) -> np.ndarray:
+    """Equaliser scale factors, uint32 [F][N], unsigned fix_18_7 integers
+    around `center` (320 = 2.5: a fix_18_17 sigma of 2^14 then lands at an
+    RMS of 2.5 codes), +-spread relative."""
+    r = _rng(seed, (5,))
+    g = center * (1.0 + r.uniform(-spread, spread, size=(n_chans, n_inputs)))
+    return np.clip(np.rint(g), 0, (1 << 18) - 1).astype(np.uint32)
