@@ -23,6 +23,9 @@ Other workloads (one JSON line each, same keys plus a comparison):
                       step, against 12 plain correlate + dump calls on the
                       same stream; both autotuned first; outputs compared
                       bit for bit.
+  --workload requant  the F stage's equaliser / 4-bit requantiser at the
+                      cylinder shape (PFB words [8192][1024][192] -> packed
+                      bytes), HBM-bound: samples/s and GB/s against 8 TB/s.
   --workload stream   four sub-arrays (N=192/96/32/32, F=1024/1024/1024/256)
                       in two waves under a memory budget that makes the
                       second wave wait: saturating throughput of the serving
@@ -124,7 +127,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "dish", "dish_tiny", "batch", "stream"])
+    ap.add_argument("--workload", default="cylinder",
+                    choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant"])
     ap.add_argument("--stream-dumps", type=int, default=4, help="dumps per request (stream, saturating)")
     ap.add_argument("--paced-seconds", type=float, default=6.0, help="length of the paced run (stream)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -156,6 +160,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "stream":
         return bench_stream(args)
+    if args.workload == "requant":
+        return bench_requant(args)
 
     w = synth.WORKLOADS[args.workload]
     N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
@@ -423,6 +429,66 @@ def bench_stream(args) -> int:
         "paced": {"seconds": t_paced, **lat, "per_subarray": per},
         "roofline": None, "cpu_baseline": None,
     })
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def bench_requant(args) -> int:
+    """Equaliser / 4-bit requantiser at the cylinder shape."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1904_07778_amd.xeng import requantize
+
+    T, F, N = 8192, 1024, 192
+    log(f"requant workload: words [{T}][{F}][{N}] ({T * F * N * 8 / 1e9:.1f} GB)")
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    z = torch.randn((T, F, N, 2), device="cuda", generator=gen) * 2.0**14
+    v = z.round().clamp(-(2**17), 2**17 - 1).to(torch.int64) & 0x3FFFF
+    del z
+    words = (v[..., 0] << 18) | v[..., 1]
+    del v
+    gains_h = synth.eq_gains(5, N, F)
+    gains = torch.from_numpy(gains_h.view(np.int32)).cuda()
+    out = torch.empty((T, F, N), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            requantize(words, gains, out=out, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        requantize(words, gains, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    kms = e0.elapsed_time(e1) / args.steps
+    n = T * F * N
+    nbytes = n * 9 + F * N * 4
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import requant as R
+        rows = 0
+        c0 = time.perf_counter()
+        while rows < T and time.perf_counter() - c0 < args.cpu_seconds:
+            R.requantize(words[rows:rows + 8].cpu().numpy().view(np.uint64), gains_h)
+            rows += 8
+        dt = time.perf_counter() - c0
+        cpu = {"value": rows * F * N / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+               "sample": f"{rows} of {T} time rows (F={F}, N={N}), {dt:.1f} s, numpy"}
+    rec = _base_record(args, "equaliser / 4-bit requantiser complex samples/s (F stage, cylinder shape)",
+                       n / (ms / 1e3), ms,
+                       {"workload": f"requant: PFB words [{T}][{F}][{N}] fix_18_17, gains fix_18_7 -> packed 4+4-bit",
+                        "n_time": T, "n_chans": F, "n_inputs": N})
+    rec.update({"unit": "samples/s", "dtype": "int32", "kernel_ms": kms,
+                "roofline": {"bound": "hbm", "achieved": nbytes / (kms / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": nbytes / (kms / 1e3) / 1e9 / PEAK_HBM_GBS,
+                             "traffic": None, "algorithmic_bytes": nbytes},
+                "cpu_baseline": cpu})
     print(json.dumps(rec), flush=True)
     return 0
 

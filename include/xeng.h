@@ -176,6 +176,26 @@ int64_t xeng_accumulator_bytes(int32_t n_inputs, int32_t n_chans);
 int xeng_autotune(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64_t *n_time,
                   int32_t reps, float *best_ms);
 
+/*
+ * xeng_requantize - equaliser / 4-bit requantiser of the F stage (Sec. 2.1),
+ * the step that produces the X-engine's input.  Stateless, asynchronous on
+ * hip_stream (NULL: the default stream).
+ *   d_words   uint64 [n_time][n_chans][n_inputs], device, 8-byte aligned: PFB
+ *             output words, 18-bit two's-complement real part (fix_18_17) in
+ *             bits 35..18, imaginary part in bits 17..0; higher bits ignored.
+ *   d_gains   uint32 [n_chans][n_inputs], device, 4-byte aligned: scale
+ *             factors, unsigned fix_18_7 in the low 18 bits (higher ignored).
+ *   d_out     uint8 [n_time][n_chans][n_inputs], device: packed 4+4-bit
+ *             samples, the X-engine's input (real part in bits 7..4).
+ * Each part times its gain (a fix_36_24 product) is rounded half to even at
+ * the fix_4_3 LSB and saturated to -7 .. 7 (1.001b .. 0.111b).  Exact.
+ * Buffers are caller-owned.  n_time == 0 is a no-op.  Errors: EINVAL (null or
+ * misaligned pointer, n_chans or n_inputs < 1, n_time < 0, grid too large),
+ * EDEVICE (launch failure).
+ */
+int xeng_requantize(const uint64_t *d_words, const uint32_t *d_gains, uint8_t *d_out,
+                    int64_t n_time, int32_t n_chans, int32_t n_inputs, void *hip_stream);
+
 /* xeng_destroy - wait for the plan's work, free everything it owns.  NULL is a no-op. */
 void xeng_destroy(xeng_plan_t *p);
 

@@ -65,6 +65,8 @@ _lib.xeng_accumulator_bytes.restype = ctypes.c_int64
 _lib.xeng_autotune.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_float)]
 _lib.xeng_autotune.restype = ctypes.c_int
+_lib.xeng_requantize.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P]
+_lib.xeng_requantize.restype = ctypes.c_int
 
 
 class XengError(RuntimeError):
@@ -169,6 +171,33 @@ def xeng_last_error(plan: int) -> str:
 
 def xeng_integrated(plan: int, array: int) -> int:
     return int(_lib.xeng_integrated(plan, array))
+
+
+def xeng_requantize(words, gains, out, n_time: int, n_chans: int, n_inputs: int, stream=None) -> None:
+    s = getattr(stream, "cuda_stream", stream)
+    _check(_lib.xeng_requantize(_ptr(words), _ptr(gains), _ptr(out), n_time, n_chans, n_inputs, s))
+
+
+def requantize(words, gains, out=None, stream=None):
+    """Equaliser / 4-bit requantiser (F stage): PFB words int64 (or uint64)
+    [T, F, N] and gains int32 (or uint32) [F, N], CUDA tensors, -> packed
+    uint8 [T, F, N], the X-engine's input.  Runs on `stream` (default: the
+    current stream)."""
+    import torch
+    if words.dim() != 3 or gains.shape != words.shape[1:]:
+        raise ValueError(f"words [T, F, N] and gains [F, N] expected, got {tuple(words.shape)} and {tuple(gains.shape)}")
+    if words.element_size() != 8 or gains.element_size() != 4 or not (words.is_cuda and gains.is_cuda):
+        raise ValueError("words must be 8-byte and gains 4-byte integer CUDA tensors")
+    if not (words.is_contiguous() and gains.is_contiguous()):
+        raise ValueError("words and gains must be contiguous")
+    T, F, N = words.shape
+    if out is None:
+        out = torch.empty((T, F, N), dtype=torch.uint8, device=words.device)
+    elif out.shape != words.shape or out.dtype != torch.uint8 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 tensor shaped like words")
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    xeng_requantize(words, gains, out, T, F, N, stream)
+    return out
 
 
 # ------------------------------------------------------------ tensor wrapper

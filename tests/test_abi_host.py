@@ -85,3 +85,14 @@ def test_plan_flags_and_empty_plans():
     with pytest.raises(X.XengError) as e:
         X.xeng_plan([(8, 4, 10)], flags=1 << 5)   # unknown flag
     assert e.value.status == X.XENG_EINVAL
+
+
+def test_requantize_argument_checks_without_device():
+    from paper_1904_07778_amd import xeng as X
+    lib = X._lib
+    assert lib.xeng_requantize(None, None, None, 1, 1, 1, None) == X.XENG_EINVAL
+    assert lib.xeng_requantize(8, 4, 16, -1, 1, 1, None) == X.XENG_EINVAL     # n_time < 0
+    assert lib.xeng_requantize(8, 4, 16, 1, 0, 1, None) == X.XENG_EINVAL      # no channels
+    assert lib.xeng_requantize(9, 4, 16, 1, 1, 1, None) == X.XENG_EINVAL      # words misaligned
+    assert lib.xeng_requantize(8, 6, 16, 1, 1, 1, None) == X.XENG_EINVAL      # gains misaligned
+    assert lib.xeng_requantize(8, 4, 16, 0, 1, 1, None) == X.XENG_OK          # nothing to do
