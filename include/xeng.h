@@ -196,6 +196,25 @@ int xeng_autotune(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64_
 int xeng_requantize(const uint64_t *d_words, const uint32_t *d_gains, uint8_t *d_out,
                     int64_t n_time, int32_t n_chans, int32_t n_inputs, void *hip_stream);
 
+/*
+ * xeng_eq_update - equaliser gains from the X-engine's autocorrelations
+ * (Sec. 2.1, Eq. 3: RMS = sqrt(P / 2N), P the integrated auto power over N
+ * samples), so that the 4-bit RMS comes to target_rms_x16 / 16 (the paper
+ * aims at 2..3).  Stateless, asynchronous on hip_stream.
+ *   d_vis          int32 [n_chans][N(N+1)/2][2], device: a dump of the
+ *                  requantised data (only the autos Re V_ii are read).
+ *   n_integrated   N, the dump's sample count (1 .. XENG_MAX_INTEGRATION).
+ *   d_gains_in     uint32 [n_chans][n_inputs], device: the gains used (fix_18_7).
+ *   d_gains_out    uint32 [n_chans][n_inputs], device (may equal d_gains_in).
+ *   target_rms_x16 1 .. 255.
+ * G' = G * t * sqrt(2 N / P), t = target / 16, rounded to the nearest integer
+ * (halves up) exactly, clamped to [1, 2^18 - 1]; inputs with P = 0 keep
+ * their word.  Errors: EINVAL, EDEVICE.
+ */
+int xeng_eq_update(const int32_t *d_vis, int64_t n_integrated, const uint32_t *d_gains_in,
+                   uint32_t *d_gains_out, int32_t n_chans, int32_t n_inputs, int32_t target_rms_x16,
+                   void *hip_stream);
+
 /* xeng_destroy - wait for the plan's work, free everything it owns.  NULL is a no-op. */
 void xeng_destroy(xeng_plan_t *p);
 

@@ -53,3 +53,29 @@ def requantize(words: np.ndarray, gains: np.ndarray) -> np.ndarray:
     g = np.asarray(gains).astype(np.int64)[None, :, :]
     qr, qi = requantize_value(re, g), requantize_value(im, g)
     return (((qr & 0xF) << 4) | (qi & 0xF)).astype(np.uint8)
+
+
+def eq_update(vis: np.ndarray, n_integrated: int, gains: np.ndarray, target_x16: int) -> np.ndarray:
+    """New equaliser gains from the autocorrelations (paper Sec. 2.1, Eq. 3).
+
+    RMS_i = sqrt(P_i / (2 N)) with P_i the integrated auto power of input i
+    (Re V_ii) over N samples.  The 4-bit RMS scales with the gain, so the
+    gain that brings it to the target t = target_x16 / 16 is
+    G' = G t / RMS = G t sqrt(2 N / P).  G' is rounded to the nearest
+    integer (fix_18_7 units, halves up) exactly: with M = 8 G^2 t^2 N / P,
+    round(sqrt(M) / 2) = (isqrt(floor(M)) + 1) // 2; then clamped to
+    [1, 2^18 - 1].  Inputs with P = 0 keep their gain."""
+    import math
+    F, nbl, _ = vis.shape
+    N = int((math.isqrt(8 * nbl + 1) - 1) // 2)
+    out = np.array(gains, dtype=np.uint32, copy=True)
+    for f in range(F):
+        for i in range(N):
+            P = int(vis[f, i * (i + 1) // 2 + i, 0])
+            G = int(gains[f, i]) & 0x3FFFF
+            if P <= 0:
+                continue
+            M = (8 * G * G * target_x16 * target_x16 * n_integrated) // (P * 256)
+            k = (math.isqrt(M) + 1) // 2
+            out[f, i] = min(max(k, 1), (1 << 18) - 1)
+    return out

@@ -1,6 +1,7 @@
 // k_requant.hip - equaliser / 4-bit requantiser of the F stage (paper
-// Sec. 2.1), the step that produces the X-engine's input, and its C entry
-// point xeng_requantize (declared in include/xeng.h).
+// Sec. 2.1), the step that produces the X-engine's input, and the gain
+// update that closes the loop from the X-engine's autocorrelations (Eq. 3);
+// C entry points xeng_requantize and xeng_eq_update (include/xeng.h).
 //
 // Per complex sample: the PFB output word holds an 18-bit two's-complement
 // real part in bits 35..18 and imaginary part in bits 17..0 (fix_18_17).
@@ -104,8 +105,59 @@ __global__ __launch_bounds__(THREADS) void requant1(const uint64_t* __restrict__
   for (int64_t t = t0; t < t1; ++t) out[t * fn + x] = (uint8_t)byte_of(w[t * fn + x], g);
 }
 
+// Gain update from the autocorrelations (Eq. 3): one thread per (channel,
+// input).  G' = round(G t sqrt(2 T / P)), t = tx / 16, halves up, decided
+// exactly: a double-precision estimate k is moved until
+//     (2k - 1)^2 256 P <= 8 G^2 tx^2 T < (2k + 1)^2 256 P
+// holds, comparing 128-bit integer products.
+__global__ __launch_bounds__(THREADS) void eq_update(const int32_t* __restrict__ vis, int64_t nbl,
+                                                     int64_t T, const uint32_t* __restrict__ gin,
+                                                     uint32_t* __restrict__ gout, int F, int N, int tx) {
+  const int64_t idx = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+  if (idx >= (int64_t)F * N) return;
+  const int f = (int)(idx / N), i = (int)(idx % N);
+  const int64_t P = vis[((int64_t)f * nbl + (int64_t)i * (i + 1) / 2 + i) * 2];
+  const uint32_t word = gin[idx];
+  if (P <= 0) {
+    gout[idx] = word;
+    return;
+  }
+  const uint64_t G = word & 0x3FFFFu;
+  const unsigned __int128 rhs = (unsigned __int128)(8ull * G * G * (uint64_t)tx * (uint64_t)tx) * (uint64_t)T;
+  const uint64_t p256 = 256ull * (uint64_t)P;
+  auto lhs = [&](int64_t odd) {  // odd^2 * 256 P  (odd < 2^36, so < 2^111)
+    return (unsigned __int128)(uint64_t)odd * (uint64_t)odd * p256;
+  };
+  // |k - x| < 1e-4 for every admissible input (x < 2^35, a few roundings of
+  // relative size 2^-53), so each correction takes at most one step; the
+  // bound on the loops only guarantees that every lane finishes.
+  const double xd = (double)G * tx * sqrt(2.0 * (double)T / (double)P) / 16.0;
+  int64_t k = (int64_t)floor(xd + 0.5);
+  if (k < 0) k = 0;
+  for (int it = 0; it < 4 && k > 0 && lhs(2 * k - 1) > rhs; ++it) --k;
+  for (int it = 0; it < 4 && lhs(2 * k + 1) <= rhs; ++it) ++k;
+  gout[idx] = (uint32_t)min<int64_t>(max<int64_t>(k, 1), (1 << 18) - 1);
+}
+
 }  // namespace
 }  // namespace xeng
+
+extern "C" int xeng_eq_update(const int32_t* d_vis, int64_t n_integrated, const uint32_t* d_gains_in,
+                              uint32_t* d_gains_out, int32_t n_chans, int32_t n_inputs,
+                              int32_t target_rms_x16, void* hip_stream) {
+  if (!d_vis || !d_gains_in || !d_gains_out || n_integrated < 1 || n_integrated > XENG_MAX_INTEGRATION ||
+      n_chans < 1 || n_inputs < 1 || n_inputs > XENG_MAX_INPUTS || target_rms_x16 < 1 ||
+      target_rms_x16 > 255)
+    return XENG_EINVAL;
+  const int64_t n = (int64_t)n_chans * n_inputs;
+  const int64_t blocks = (n + xeng::THREADS - 1) / xeng::THREADS;
+  if (blocks > 2147483647LL) return XENG_EINVAL;
+  const int64_t nbl = (int64_t)n_inputs * (n_inputs + 1) / 2;
+  hipLaunchKernelGGL(xeng::eq_update, dim3((unsigned)blocks), dim3(xeng::THREADS), 0,
+                     reinterpret_cast<hipStream_t>(hip_stream), d_vis, nbl, n_integrated, d_gains_in,
+                     d_gains_out, n_chans, n_inputs, target_rms_x16);
+  return hipGetLastError() == hipSuccess ? XENG_OK : XENG_EDEVICE;
+}
 
 extern "C" int xeng_requantize(const uint64_t* d_words, const uint32_t* d_gains, uint8_t* d_out,
                                int64_t n_time, int32_t n_chans, int32_t n_inputs, void* hip_stream) {

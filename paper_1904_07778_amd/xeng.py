@@ -67,6 +67,8 @@ _lib.xeng_autotune.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_i
 _lib.xeng_autotune.restype = ctypes.c_int
 _lib.xeng_requantize.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P]
 _lib.xeng_requantize.restype = ctypes.c_int
+_lib.xeng_eq_update.argtypes = [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]
+_lib.xeng_eq_update.restype = ctypes.c_int
 
 
 class XengError(RuntimeError):
@@ -197,6 +199,30 @@ def requantize(words, gains, out=None, stream=None):
         raise ValueError("out must be a contiguous uint8 tensor shaped like words")
     stream = stream if stream is not None else torch.cuda.current_stream()
     xeng_requantize(words, gains, out, T, F, N, stream)
+    return out
+
+
+def xeng_eq_update(vis, n_integrated: int, gains_in, gains_out, n_chans: int, n_inputs: int,
+                   target_rms_x16: int, stream=None) -> None:
+    s = getattr(stream, "cuda_stream", stream)
+    _check(_lib.xeng_eq_update(_ptr(vis), n_integrated, _ptr(gains_in), _ptr(gains_out), n_chans, n_inputs,
+                               target_rms_x16, s))
+
+
+def eq_update(vis, n_integrated: int, gains, target_rms: float = 2.5, out=None, stream=None):
+    """New equaliser gains (int32 [F, N] CUDA tensor, fix_18_7) from a dump
+    of the requantised data (int32 [F, nbl, 2] CUDA tensor), so that the
+    4-bit RMS comes to target_rms (a multiple of 1/16)."""
+    import torch
+    F, N = gains.shape
+    if vis.dim() != 3 or vis.shape[0] != F or vis.shape[1] != N * (N + 1) // 2 or vis.dtype != torch.int32:
+        raise ValueError("vis must be an int32 [F, N(N+1)/2, 2] dump matching gains [F, N]")
+    if gains.element_size() != 4 or not (vis.is_cuda and gains.is_cuda and vis.is_contiguous() and gains.is_contiguous()):
+        raise ValueError("gains must be a contiguous 4-byte CUDA tensor")
+    tx = int(round(target_rms * 16))
+    out = torch.empty_like(gains) if out is None else out
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    xeng_eq_update(vis, n_integrated, gains, out, F, N, tx, stream)
     return out
 
 

@@ -100,3 +100,46 @@ def test_end_to_end_into_the_x_engine():
         vis, _ = p.dump(to_host=True)
     want = oracle.correlate(R.requantize(words, gains))
     assert np.array_equal(vis[0].numpy(), want), first_mismatch(vis[0].numpy(), want)
+
+
+def test_eq_update_matches_oracle_on_extremes():
+    import torch
+    from paper_1904_07778_amd.xeng import eq_update
+    rng = np.random.default_rng(41)
+    F, N = 7, 33
+    nbl = N * (N + 1) // 2
+    print("eq_update extremes", flush=True)
+    for T in (1, 4096, 16777215):
+        vis = rng.integers(-2**31, 2**31 - 1, size=(F, nbl, 2), dtype=np.int64).astype(np.int32)
+        autos = [i * (i + 1) // 2 + i for i in range(N)]
+        P = rng.integers(1, 2**31 - 1, size=(F, N))
+        P[:, :3] = [1, 0, 2**31 - 1]                      # smallest, silent, largest auto power
+        vis[:, autos, 0] = P
+        gains = rng.integers(0, 2**32, size=(F, N), dtype=np.uint64).astype(np.uint32)
+        for tx in (1, 40, 255):
+            got = eq_update(torch.from_numpy(vis).cuda(), T, torch.from_numpy(gains.view(np.int32)).cuda(),
+                            target_rms=tx / 16).cpu().numpy().view(np.uint32)
+            want = R.eq_update(vis, T, gains, tx)
+            assert np.array_equal(got, want), f"T={T} tx={tx}: " + first_mismatch(got, want)
+
+
+def test_closed_loop_brings_rms_into_the_paper_band():
+    """F -> X -> gains -> F: start with the 4-bit RMS near 1 on half the
+    inputs and near 4.3 (clipping) on the others; one update puts every
+    input in the 2..3 band of Sec. 2.1, and it stays there."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan, eq_update, requantize
+    T, F, N = 4096, 16, 48
+    print("closed loop", flush=True)
+    words = torch.from_numpy(synth.pfb_words(8, N, F, T, sigma=2.0**12).view(np.int64)).cuda()
+    g0 = np.where(np.arange(N) % 2 == 0, 512, 2200).astype(np.int32)   # sigma 2^12: RMS ~1 and ~4.3
+    gains = torch.from_numpy(np.tile(g0, (F, 1))).cuda()
+    for it in range(3):
+        with Plan([(N, F, T)]) as p:
+            p.correlate([requantize(words, gains)])
+            vis, n = p.dump()
+        autos = vis[0][:, [i * (i + 1) // 2 + i for i in range(N)], 0].double()
+        rms = torch.sqrt(autos / (2 * T))
+        if it > 0:
+            assert float(rms.min()) > 2.0 and float(rms.max()) < 3.0, (it, float(rms.min()), float(rms.max()))
+        gains = eq_update(vis[0], n[0], gains, target_rms=2.5)

@@ -71,3 +71,38 @@ def test_paper_rms_band():
     im = ((out & 15).astype(np.int16) ^ 8) - 8
     rms = np.sqrt(0.5 * np.mean(re.astype(float) ** 2 + im.astype(float) ** 2))
     assert 2.0 < rms < 3.0
+
+
+def test_eq_update_exact_rounding_and_closed_form():
+    from fractions import Fraction
+    import math
+    rng = np.random.default_rng(9)
+    F, N, T = 3, 5, 4096
+    vis = np.zeros((F, N * (N + 1) // 2, 2), dtype=np.int32)
+    gains = rng.integers(1, 1 << 18, size=(F, N)).astype(np.uint32)
+    P = rng.integers(1, 128 * T, size=(F, N))
+    for i in range(N):
+        vis[:, i * (i + 1) // 2 + i, 0] = P[:, i]
+    vis[1, 2 * 3 // 2 + 2, 0] = 0                      # a silent input keeps its gain
+    got = R.eq_update(vis, T, gains, 40)               # target 2.5
+    for f in range(F):
+        for i in range(N):
+            p = int(vis[f, i * (i + 1) // 2 + i, 0])
+            if p == 0:
+                assert got[f, i] == gains[f, i]
+                continue
+            # restatement: nearest integer to G t sqrt(2 N / P), from exact
+            # rational bounds (no float): k minimises |k^2 ... |, checked by
+            # bracketing (k - 1/2)^2 <= (G t)^2 2N/P < (k + 1/2)^2
+            x2 = Fraction(int(gains[f, i]) ** 2 * 25 * 2 * T, 4 * p)
+            k = int(got[f, i])
+            if 1 < k < (1 << 18) - 1:
+                assert Fraction(2 * k - 1, 2) ** 2 <= x2 < Fraction(2 * k + 1, 2) ** 2
+    # closed form: RMS already at the target -> gain unchanged
+    g0 = np.full((1, 1), 320, dtype=np.uint32)
+    v0 = np.zeros((1, 1, 2), dtype=np.int32)
+    v0[0, 0, 0] = 2 * 1000 * (5 * 5) // 4             # RMS = 2.5 exactly over N = 1000
+    assert R.eq_update(v0, 1000, g0, 40)[0, 0] == 320
+    # RMS twice the target -> gain halves
+    v0[0, 0, 0] = 2 * 1000 * 25                        # RMS = 5
+    assert R.eq_update(v0, 1000, g0, 40)[0, 0] == 160
