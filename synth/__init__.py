@@ -193,3 +193,23 @@ def eq_gains(seed: int, n_inputs: int, n_chans: int, center: float = 320.0, spre
     r = _rng(seed, (5,))
     g = center * (1.0 + r.uniform(-spread, spread, size=(n_chans, n_inputs)))
     return np.clip(np.rint(g), 0, (1 << 18) - 1).astype(np.uint32)
+
+
+def packets(block: np.ndarray, mcnt0: int, xid: int, stride: int | None = None) -> np.ndarray:
+    """Cut a voltage block uint8 [8 M][F][32 B] into the F engine's packets
+    (one per time block of 8 samples and board of 32 inputs), each an 8-byte
+    header (6-byte big-endian counter, board id, band id) followed by the
+    [8][F][32] payload, padded to `stride` bytes.  Packets are in (counter,
+    board) order; tests shuffle, drop and duplicate them."""
+    T, F, N = block.shape
+    M, B = T // 8, N // 32
+    pay = 8 * F * 32
+    stride = stride or 8 + pay
+    out = np.zeros((M * B, stride), dtype=np.uint8)
+    for m in range(M):
+        for b in range(B):
+            row = out[m * B + b]
+            row[:6] = np.frombuffer((mcnt0 + m).to_bytes(6, "big"), dtype=np.uint8)
+            row[6], row[7] = b, xid
+            row[8:8 + pay] = block[8 * m:8 * m + 8, :, 32 * b:32 * b + 32].reshape(-1)
+    return out
