@@ -26,6 +26,10 @@ Other workloads (one JSON line each, same keys plus a comparison):
   --workload requant  the F stage's equaliser / 4-bit requantiser at the
                       cylinder shape (PFB words [8192][1024][192] -> packed
                       bytes), HBM-bound: samples/s and GB/s against 8 TB/s.
+  --workload ingest   packet ingest / corner turn: 16384 time blocks x 8
+                      boards x 32 channels of the paper's 8208-byte packets,
+                      shuffled with 1% loss -> the X-engine's input block
+                      (HBM-bound).
   --workload stream   four sub-arrays (N=192/96/32/32, F=1024/1024/1024/256)
                       in two waves under a memory budget that makes the
                       second wave wait: saturating throughput of the serving
@@ -128,7 +132,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cylinder",
-                    choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant"])
+                    choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant", "ingest"])
     ap.add_argument("--stream-dumps", type=int, default=4, help="dumps per request (stream, saturating)")
     ap.add_argument("--paced-seconds", type=float, default=6.0, help="length of the paced run (stream)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -162,6 +166,8 @@ def main() -> int:
         return bench_stream(args)
     if args.workload == "requant":
         return bench_requant(args)
+    if args.workload == "ingest":
+        return bench_ingest(args)
 
     w = synth.WORKLOADS[args.workload]
     N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
@@ -429,6 +435,56 @@ def bench_stream(args) -> int:
         "paced": {"seconds": t_paced, **lat, "per_subarray": per},
         "roofline": None, "cpu_baseline": None,
     })
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def bench_ingest(args) -> int:
+    """Packet ingest and corner turn at the paper's packet size."""
+    import numpy as np
+    import torch
+
+    from paper_1904_07778_amd.xeng import ingest
+
+    blocks, boards, chans = 16384, 8, 32
+    pay = 8 * chans * 32
+    stride = 8 + pay
+    n = blocks * boards
+    log(f"ingest workload: {n} packets of {stride} bytes ({n * stride / 1e9:.2f} GB)")
+    g = torch.Generator(device="cuda").manual_seed(11)
+    order = torch.randperm(n, device="cuda", generator=g)[: n - n // 100]   # shuffled, 1% lost
+    pk = torch.randint(0, 256, (order.numel(), stride), dtype=torch.uint8, device="cuda", generator=g)
+    m = (order // boards).to(torch.int64) + 1000
+    b = (order % boards).to(torch.int64)
+    for k in range(6):
+        pk[:, k] = ((m >> (8 * (5 - k))) & 0xFF).to(torch.uint8)
+    pk[:, 6] = b.to(torch.uint8)
+    pk[:, 7] = 3
+    out = torch.empty((8 * blocks, chans, 32 * boards), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        ingest(pk, 1000, blocks, boards, chans, 3, out=out, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ingest(pk, 1000, blocks, boards, chans, 3, out=out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    kms = e0.elapsed_time(e1) / args.steps
+    nbytes = order.numel() * stride + out.numel()           # packets read once, block written once
+    rec = _base_record(args, "packet ingest / corner turn bytes/s (8208-byte packets -> X-engine block)",
+                       nbytes / (ms / 1e3), ms,
+                       {"workload": f"ingest: {blocks} time blocks x {boards} boards x {chans} channels, "
+                                    "shuffled, 1% lost", "packets": int(order.numel())})
+    rec.update({"unit": "B/s", "dtype": "u8", "kernel_ms": kms,
+                "roofline": {"bound": "hbm", "achieved": nbytes / (kms / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": nbytes / (kms / 1e3) / 1e9 / PEAK_HBM_GBS,
+                             "traffic": None, "algorithmic_bytes": nbytes},
+                "cpu_baseline": None})
     print(json.dumps(rec), flush=True)
     return 0
 

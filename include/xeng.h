@@ -215,6 +215,35 @@ int xeng_eq_update(const int32_t *d_vis, int64_t n_integrated, const uint32_t *d
                    uint32_t *d_gains_out, int32_t n_chans, int32_t n_inputs, int32_t target_rms_x16,
                    void *hip_stream);
 
+/*
+ * xeng_ingest - packet ingest and corner turn on the X side (Sec. 2.3,
+ * Sec. 2.1): assemble one integration block from the F engine's packets.
+ * Stateless, asynchronous on hip_stream.
+ *   d_packets      n_packets packets, device, 8-byte aligned, packet_stride
+ *                  bytes apart (a multiple of 8, >= 8 + 8 * n_chans * 32).
+ *                  Each: 6-byte big-endian counter MCNT, 1 byte Fid (board),
+ *                  1 byte Xid (band), then uint8 [8][n_chans][32] samples
+ *                  of the board's 32 inputs ([time, channel, input]).
+ *   mcnt0          counter of the first time block (0 .. 2^48 - 1).
+ *   n_blocks       time blocks of 8 samples in the output (1 .. 65535).
+ *   n_boards       boards (inputs 32 Fid .. 32 Fid + 31), 32 n_boards <=
+ *                  XENG_MAX_INPUTS.
+ *   n_chans        channels per packet (32 for a 1024-point spectrum on 32
+ *                  bands, 16 for 512).
+ *   xid            this node's band: packets of other bands are ignored.
+ *   d_index        int32 [n_blocks][n_boards], device, out: the packet
+ *                  number that filled each (time block, board) tile, or -1
+ *                  where none arrived (loss; its samples are zero).
+ *   d_out          uint8 [8 n_blocks][n_chans][32 n_boards], device, 8-byte
+ *                  aligned, out: the X-engine's input block.
+ * Packets outside [mcnt0, mcnt0 + n_blocks), of a board >= n_boards or of
+ * another band are ignored; of two packets for one tile the later in the
+ * buffer wins.  Errors: EINVAL (sizes, alignment, null pointers), EDEVICE.
+ */
+int xeng_ingest(const uint8_t *d_packets, int64_t n_packets, int32_t packet_stride, int64_t mcnt0,
+                int32_t n_blocks, int32_t n_boards, int32_t n_chans, int32_t xid, int32_t *d_index,
+                uint8_t *d_out, void *hip_stream);
+
 /* xeng_destroy - wait for the plan's work, free everything it owns.  NULL is a no-op. */
 void xeng_destroy(xeng_plan_t *p);
 

@@ -69,6 +69,9 @@ _lib.xeng_requantize.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, cty
 _lib.xeng_requantize.restype = ctypes.c_int
 _lib.xeng_eq_update.argtypes = [_P, ctypes.c_int64, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]
 _lib.xeng_eq_update.restype = ctypes.c_int
+_lib.xeng_ingest.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
+_lib.xeng_ingest.restype = ctypes.c_int
 
 
 class XengError(RuntimeError):
@@ -224,6 +227,31 @@ def eq_update(vis, n_integrated: int, gains, target_rms: float = 2.5, out=None, 
     stream = stream if stream is not None else torch.cuda.current_stream()
     xeng_eq_update(vis, n_integrated, gains, out, F, N, tx, stream)
     return out
+
+
+def xeng_ingest(packets, n_packets: int, packet_stride: int, mcnt0: int, n_blocks: int, n_boards: int,
+                n_chans: int, xid: int, index, out, stream=None) -> None:
+    s = getattr(stream, "cuda_stream", stream)
+    _check(_lib.xeng_ingest(_ptr(packets), n_packets, packet_stride, mcnt0, n_blocks, n_boards, n_chans, xid,
+                            _ptr(index), _ptr(out), s))
+
+
+def ingest(packets, mcnt0: int, n_blocks: int, n_boards: int, n_chans: int, xid: int, out=None, stream=None):
+    """Assemble an integration block from packets (uint8 CUDA tensor
+    [n_packets, stride]); returns (uint8 [8 n_blocks, n_chans, 32 n_boards],
+    int32 index [n_blocks, n_boards] with -1 for lost packets)."""
+    import torch
+    if packets.dim() != 2 or packets.dtype != torch.uint8 or not packets.is_cuda or not packets.is_contiguous():
+        raise ValueError("packets must be a contiguous uint8 CUDA tensor [n_packets, stride]")
+    shape = (8 * n_blocks, n_chans, 32 * n_boards)
+    out = torch.empty(shape, dtype=torch.uint8, device=packets.device) if out is None else out
+    if tuple(out.shape) != shape or out.dtype != torch.uint8 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous uint8 tensor {shape}")
+    index = torch.empty((n_blocks, n_boards), dtype=torch.int32, device=packets.device)
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    xeng_ingest(packets if packets.shape[0] else None, packets.shape[0], packets.shape[1], mcnt0, n_blocks,
+                n_boards, n_chans, xid, index, out, stream)
+    return out, index
 
 
 # ------------------------------------------------------------ tensor wrapper

@@ -96,3 +96,21 @@ def test_requantize_argument_checks_without_device():
     assert lib.xeng_requantize(9, 4, 16, 1, 1, 1, None) == X.XENG_EINVAL      # words misaligned
     assert lib.xeng_requantize(8, 6, 16, 1, 1, 1, None) == X.XENG_EINVAL      # gains misaligned
     assert lib.xeng_requantize(8, 4, 16, 0, 1, 1, None) == X.XENG_OK          # nothing to do
+
+
+def test_ingest_argument_checks_without_device():
+    from paper_1904_07778_amd import xeng as X
+    lib = X._lib
+    ok = dict(n_packets=1, stride=8 + 8 * 32 * 32, mcnt0=0, blocks=1, boards=1, chans=32, xid=0)
+    def call(pk=8, idx=4, out=8, **kw):
+        a = dict(ok, **kw)
+        return lib.xeng_ingest(pk, a["n_packets"], a["stride"], a["mcnt0"], a["blocks"], a["boards"],
+                               a["chans"], a["xid"], idx, out, None)
+    assert call(idx=None) == X.XENG_EINVAL
+    assert call(stride=8 + 8 * 32 * 32 - 8) == X.XENG_EINVAL      # payload does not fit
+    assert call(stride=8 + 8 * 32 * 32 + 4) == X.XENG_EINVAL      # not a multiple of 8
+    assert call(boards=9) == X.XENG_EINVAL                        # 288 inputs
+    assert call(xid=256) == X.XENG_EINVAL
+    assert call(mcnt0=1 << 48) == X.XENG_EINVAL
+    assert call(pk=12) == X.XENG_EINVAL                           # misaligned packets
+    assert call(blocks=65536) == X.XENG_EINVAL
