@@ -30,6 +30,9 @@ Other workloads (one JSON line each, same keys plus a comparison):
                       boards x 32 channels of the paper's 8208-byte packets,
                       shuffled with 1% loss -> the X-engine's input block
                       (HBM-bound).
+  --workload chan     F-stage channeliser at the cylinder shape: 192 int8 ADC
+                      streams -> 8192 spectra of 1024 channels (4-tap PFB,
+                      2048-point FFT per input pair), float32.
   --workload stream   four sub-arrays (N=192/96/32/32, F=1024/1024/1024/256)
                       in two waves under a memory budget that makes the
                       second wave wait: saturating throughput of the serving
@@ -132,7 +135,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cylinder",
-                    choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant", "ingest"])
+                    choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant", "ingest", "chan"])
     ap.add_argument("--stream-dumps", type=int, default=4, help="dumps per request (stream, saturating)")
     ap.add_argument("--paced-seconds", type=float, default=6.0, help="length of the paced run (stream)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -168,6 +171,8 @@ def main() -> int:
         return bench_requant(args)
     if args.workload == "ingest":
         return bench_ingest(args)
+    if args.workload == "chan":
+        return bench_chan(args)
 
     w = synth.WORKLOADS[args.workload]
     N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
@@ -435,6 +440,49 @@ def bench_stream(args) -> int:
         "paced": {"seconds": t_paced, **lat, "per_subarray": per},
         "roofline": None, "cpu_baseline": None,
     })
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def bench_chan(args) -> int:
+    """F-stage channeliser at the cylinder shape."""
+    import torch
+
+    from paper_1904_07778_amd.xeng import channelise
+
+    N, F, S = 192, 1024, 8192
+    n_samples = 2 * F * (S + 3)
+    log(f"chan workload: {N} streams x {n_samples} samples -> [{S}][{F}][{N}] complex64")
+    g = torch.Generator(device="cuda").manual_seed(13)
+    adc = (torch.randn((N, n_samples), device="cuda", generator=g) * 20).round().clamp(-128, 127).to(torch.int8)
+    out = torch.empty((S, F, N), dtype=torch.complex64, device="cuda")
+    tables = torch.empty(4 * 2 * F + 2 * F, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        channelise(adc, F, out=out, tables=tables, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        channelise(adc, F, out=out, tables=tables, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    kms = e0.elapsed_time(e1) / args.steps
+    nbytes = adc.numel() + out.numel() * 8
+    flops = (N // 2) * S * (5 * 2 * F * 11 + 8 * 2 * 2 * F)   # FFT + 4-tap FIR on two streams
+    rec = _base_record(args, "F-stage channeliser input samples/s (cylinder shape, 1024 channels)",
+                       adc.numel() / (ms / 1e3), ms,
+                       {"workload": f"chan: {N} int8 streams, {S} spectra of {F} channels, 4-tap PFB, "
+                                    "two real inputs per complex FFT", "n_inputs": N, "n_chans": F, "spectra": S})
+    rec.update({"unit": "samples/s", "dtype": "f32", "kernel_ms": kms,
+                "roofline": {"bound": "hbm", "achieved": nbytes / (kms / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": nbytes / (kms / 1e3) / 1e9 / PEAK_HBM_GBS,
+                             "traffic": None, "algorithmic_bytes": nbytes,
+                             "fp32_tflops": flops / (kms / 1e3) / 1e12},
+                "cpu_baseline": None})
     print(json.dumps(rec), flush=True)
     return 0
 

@@ -244,6 +244,34 @@ int xeng_ingest(const uint8_t *d_packets, int64_t n_packets, int32_t packet_stri
                 int32_t n_blocks, int32_t n_boards, int32_t n_chans, int32_t xid, int32_t *d_index,
                 uint8_t *d_out, void *hip_stream);
 
+/*
+ * xeng_channelise - F-stage channeliser (Sec. 2.1, Eq. 1-2): 4-tap polyphase
+ * filter bank (Hamming-windowed sinc prototype) and one complex FFT of
+ * L = 2 n_chans points per pair of real inputs (2q, 2q + 1), split by Eq. 2.
+ * Float32.  Stateless, asynchronous on hip_stream; allocates nothing.
+ *   d_adc       int8 [n_inputs][n_samples], device, 8-byte aligned: real
+ *               ADC samples, one stream per input (n_samples % 8 == 0).
+ *   n_inputs    even, >= 2.
+ *   n_chans     F, a power of two from 8 to 1024.
+ *   d_out       float [S][F][n_inputs][2], device, 16-byte aligned: complex
+ *               spectra in the X side's [time, channel, input] order;
+ *               spectrum s uses samples [2Fs, 2F(s + 4)); S from
+ *               xeng_channelise_spectra; channel k < F (Nyquist dropped).
+ *               May be NULL when there are no spectra.
+ *   d_tables    float [xeng_channelise_table_floats(F)], device, 16-byte
+ *               aligned: scratch for the filter and twiddle tables, written
+ *               by the call (caller-owned; one per concurrent call).
+ * Errors: EINVAL (sizes, alignment, null pointers), EDEVICE.
+ */
+int xeng_channelise(const int8_t *d_adc, int64_t n_samples, int32_t n_inputs, int32_t n_chans,
+                    float *d_out, float *d_tables, void *hip_stream);
+
+/* Spectra produced from n_samples samples: n_samples / 2F - 3 (>= 0); -1 on bad sizes. */
+int64_t xeng_channelise_spectra(int64_t n_samples, int32_t n_chans);
+
+/* Floats of the table scratch for F channels: 4 * 2F + 2F; -1 on bad sizes. */
+int64_t xeng_channelise_table_floats(int32_t n_chans);
+
 /* xeng_destroy - wait for the plan's work, free everything it owns.  NULL is a no-op. */
 void xeng_destroy(xeng_plan_t *p);
 

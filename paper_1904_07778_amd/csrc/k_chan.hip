@@ -1,0 +1,205 @@
+// k_chan.hip - F-stage channeliser (paper Sec. 2.1, Eq. 1-2) and its C
+// entry points (include/xeng.h).
+//
+// Per spectrum s and input pair (2q, 2q + 1) (G pairs per workgroup):
+//  1. polyphase FIR: v[n] = sum_{p<4} h[pL + n] x[sL + pL + n] for both
+//     inputs (L = 2F real samples per spectrum, h the Hamming-windowed sinc
+//     prototype), packed as y[n] = v_2q[n] + j v_2q+1[n] (Eq. 1) in LDS;
+//  2. Stockham FFT of y, L points (radix 4, and one radix-2 step when
+//     log2 L is odd), natural order out;
+//  3. Eq. 2: X_2q[k] = (Y[k] + conj Y[-k]) / 2, X_2q+1[k] = (Y[k] -
+//     conj Y[-k]) / 2j, k < F, written to out[s][k][2q .. 2q + 1] (the
+//     [time, channel, input] order of the X side).
+// Float32 arithmetic; the tables (h and the twiddles e^{-2 pi i t / L}) are
+// computed in double and rounded once.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/xeng.h"
+
+namespace xeng {
+namespace {
+
+constexpr int TAPS = 4;
+constexpr int THREADS = 256;
+constexpr int MAX_L = 2048;
+
+__global__ __launch_bounds__(THREADS) void chan_tables(float* tab, int L) {
+  const int i = blockIdx.x * THREADS + threadIdx.x;
+  const int PL = TAPS * L;
+  if (i < PL) {
+    const double w = 0.54 - 0.46 * cos(2.0 * M_PI * i / (PL - 1));
+    const double xs = (i - PL / 2.0) / L;
+    const double sinc = xs == 0.0 ? 1.0 : sinpi(xs) / (M_PI * xs);
+    tab[i] = (float)(w * sinc);
+  } else if (i < PL + L / 2) {
+    const int t = i - PL;
+    double sn, cs;
+    sincospi(2.0 * t / L, &sn, &cs);
+    tab[PL + 2 * t] = (float)cs;
+    tab[PL + 2 * t + 1] = (float)(-sn);
+  }
+}
+
+// G input pairs of one spectrum per workgroup.  G = 1 measured fastest (more
+// workgroups per CU; G = 4, with 64 contiguous output bytes per channel, was
+// slower at one workgroup per CU).  Stockham FFT (natural order, ping-pong
+// between two LDS buffers of G L points): radix-4 iterations, plus one
+// radix-2 iteration when log2 L is odd; the butterflies run in registers.
+constexpr int G_MAX = 1;
+constexpr int CTHREADS = 256;
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// e^{-2 pi i t / L} for 0 <= t < L from the half table
+__device__ __forceinline__ float2 twiddle(const float2* tw, int t, int L) {
+  const float2 w = tw[t & (L / 2 - 1)];
+  return t < L / 2 ? w : make_float2(-w.x, -w.y);
+}
+
+__global__ __launch_bounds__(CTHREADS) void channelise(const int8_t* __restrict__ adc, int64_t n_samples,
+                                                       int n_inputs, int L, int log2L, int G,
+                                                       const float* __restrict__ tab, float2* __restrict__ out) {
+  extern __shared__ float2 lds[];  // [2][G][L]
+  float2* buf0 = lds;
+  float2* buf1 = lds + G * L;
+  const int q0 = blockIdx.x * G;   // first pair
+  const int64_t s = blockIdx.y;
+  const int F = L / 2;
+  const float* h = tab;
+  const float2* tw = reinterpret_cast<const float2*>(tab + TAPS * L);
+
+  // 1. polyphase FIR of every pair, 8 consecutive samples per thread-step
+  const int steps = G * (L / 8);
+  for (int u = threadIdx.x; u < steps; u += CTHREADS) {
+    const int g = u / (L / 8), n0 = 8 * (u % (L / 8));
+    const int8_t* x0 = adc + (int64_t)(2 * (q0 + g)) * n_samples + s * L + n0;
+    const int8_t* x1 = x0 + n_samples;
+    float a[8] = {}, b[8] = {};
+#pragma unroll
+    for (int p = 0; p < TAPS; ++p) {
+      const uint2 u0 = *reinterpret_cast<const uint2*>(x0 + p * L);
+      const uint2 u1 = *reinterpret_cast<const uint2*>(x1 + p * L);
+      const float4 h0 = *reinterpret_cast<const float4*>(h + p * L + n0);
+      const float4 h1 = *reinterpret_cast<const float4*>(h + p * L + n0 + 4);
+      const float hv[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int8_t s0 = (int8_t)(((k < 4 ? u0.x : u0.y) >> (8 * (k & 3))) & 0xFF);
+        const int8_t s1 = (int8_t)(((k < 4 ? u1.x : u1.y) >> (8 * (k & 3))) & 0xFF);
+        a[k] = fmaf(hv[k], (float)s0, a[k]);
+        b[k] = fmaf(hv[k], (float)s1, b[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) buf0[g * L + n0 + k] = make_float2(a[k], b[k]);
+  }
+  __syncthreads();
+
+  // 2. Stockham iterations: sub-transform size Ns -> R Ns
+  float2* src = buf0;
+  float2* dst = buf1;
+  int Ns = 1;
+  if (log2L & 1) {  // one radix-2 iteration
+    for (int u = threadIdx.x; u < G * (L / 2); u += CTHREADS) {
+      const int g = u / (L / 2), j = u % (L / 2);
+      const float2 v0 = src[g * L + j], v1 = src[g * L + j + L / 2];
+      dst[g * L + 2 * j] = make_float2(v0.x + v1.x, v0.y + v1.y);
+      dst[g * L + 2 * j + 1] = make_float2(v0.x - v1.x, v0.y - v1.y);
+    }
+    Ns = 2;
+    float2* t = src;
+    src = dst;
+    dst = t;
+    __syncthreads();
+  }
+  for (; Ns < L; Ns <<= 2) {  // radix-4 iterations
+    const int q = L / 4;
+    for (int u = threadIdx.x; u < G * q; u += CTHREADS) {
+      const int g = u / q, j = u % q;
+      const float2* sg = src + g * L;
+      const int k = j & (Ns - 1);
+      const int t = k * (L / (4 * Ns));  // angle step of this butterfly, in units of 2 pi / L
+      const float2 v0 = sg[j];
+      const float2 v1 = cmul(sg[j + q], twiddle(tw, t, L));
+      const float2 v2 = cmul(sg[j + 2 * q], twiddle(tw, 2 * t, L));
+      const float2 v3 = cmul(sg[j + 3 * q], twiddle(tw, 3 * t, L));
+      const float2 t0 = make_float2(v0.x + v2.x, v0.y + v2.y), t1 = make_float2(v0.x - v2.x, v0.y - v2.y);
+      const float2 t2 = make_float2(v1.x + v3.x, v1.y + v3.y);
+      const float2 t3 = make_float2(v1.y - v3.y, v3.x - v1.x);  // -i (v1 - v3)
+      float2* dg = dst + g * L + ((j - k) << 2) + k;
+      dg[0] = make_float2(t0.x + t2.x, t0.y + t2.y);
+      dg[Ns] = make_float2(t1.x + t3.x, t1.y + t3.y);
+      dg[2 * Ns] = make_float2(t0.x - t2.x, t0.y - t2.y);
+      dg[3 * Ns] = make_float2(t1.x - t3.x, t1.y - t3.y);
+    }
+    float2* tmp = src;
+    src = dst;
+    dst = tmp;
+    __syncthreads();
+  }
+
+  // 3. Eq. 2 split.  Lane (k, g): the pairs of one channel are consecutive
+  //    lanes -> 16 G contiguous bytes per channel
+  float4* o = reinterpret_cast<float4*>(out + (s * F) * (int64_t)n_inputs + 2 * q0);
+  for (int u = threadIdx.x; u < G * F; u += CTHREADS) {
+    const int k = u / G, g = u % G;
+    const float2 yk = src[g * L + k], ym = src[g * L + ((L - k) & (L - 1))];
+    const float2 x1 = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y));
+    const float dr = yk.x - ym.x, di = yk.y + ym.y;   // Y[k] - conj(Y[-k])
+    o[(int64_t)k * (n_inputs / 2) + g] = make_float4(x1.x, x1.y, 0.5f * di, -0.5f * dr);
+  }
+}
+
+int log2_exact(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return (1 << l) == v ? l : -1;
+}
+
+}  // namespace
+}  // namespace xeng
+
+extern "C" int64_t xeng_channelise_spectra(int64_t n_samples, int32_t n_chans) {
+  if (n_samples < 0 || n_chans < 1) return -1;
+  const int64_t L = 2LL * n_chans;
+  const int64_t s = n_samples / L - xeng::TAPS + 1;
+  return s > 0 ? s : 0;
+}
+
+extern "C" int64_t xeng_channelise_table_floats(int32_t n_chans) {
+  if (n_chans < 1) return -1;
+  return (int64_t)xeng::TAPS * 2 * n_chans + 2 * n_chans;  // h[4L] + L/2 complex twiddles
+}
+
+extern "C" int xeng_channelise(const int8_t* d_adc, int64_t n_samples, int32_t n_inputs, int32_t n_chans,
+                               float* d_out, float* d_tables, void* hip_stream) {
+  const int L = 2 * n_chans;
+  const int log2L = xeng::log2_exact(L);
+  if (!d_adc || !d_tables || n_inputs < 2 || n_inputs % 2 || n_chans < 8 || L > xeng::MAX_L ||
+      log2L < 0 || n_samples < 0 || n_samples % 8 || (reinterpret_cast<uintptr_t>(d_adc) & 7u) ||
+      (reinterpret_cast<uintptr_t>(d_out) & 15u) || (reinterpret_cast<uintptr_t>(d_tables) & 15u))
+    return XENG_EINVAL;
+  const int64_t S = xeng_channelise_spectra(n_samples, n_chans);
+  if (S > 0 && !d_out) return XENG_EINVAL;  // (no spectra: d_out is not touched and may be null)
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const int tab_n = xeng::TAPS * L + L / 2;
+  hipLaunchKernelGGL(xeng::chan_tables, dim3((tab_n + xeng::THREADS - 1) / xeng::THREADS), dim3(xeng::THREADS),
+                     0, st, d_tables, L);
+  if (S > 0) {
+    if (S > 2147483647LL) return XENG_EINVAL;
+    const int pairs = n_inputs / 2;
+    int G = xeng::G_MAX;
+    while (pairs % G) G >>= 1;
+    const size_t lds = (size_t)2 * G * L * sizeof(float2);  // up to 128 KB
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&xeng::channelise),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return XENG_EDEVICE;
+    hipLaunchKernelGGL(xeng::channelise, dim3((unsigned)(pairs / G), (unsigned)S), dim3(xeng::CTHREADS),
+                       lds, st, d_adc, n_samples, n_inputs, L, log2L, G, d_tables,
+                       reinterpret_cast<float2*>(d_out));
+  }
+  return hipGetLastError() == hipSuccess ? XENG_OK : XENG_EDEVICE;
+}

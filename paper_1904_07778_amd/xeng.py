@@ -72,6 +72,12 @@ _lib.xeng_eq_update.restype = ctypes.c_int
 _lib.xeng_ingest.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                              ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
 _lib.xeng_ingest.restype = ctypes.c_int
+_lib.xeng_channelise.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
+_lib.xeng_channelise.restype = ctypes.c_int
+_lib.xeng_channelise_spectra.argtypes = [ctypes.c_int64, ctypes.c_int32]
+_lib.xeng_channelise_spectra.restype = ctypes.c_int64
+_lib.xeng_channelise_table_floats.argtypes = [ctypes.c_int32]
+_lib.xeng_channelise_table_floats.restype = ctypes.c_int64
 
 
 class XengError(RuntimeError):
@@ -252,6 +258,31 @@ def ingest(packets, mcnt0: int, n_blocks: int, n_boards: int, n_chans: int, xid:
     xeng_ingest(packets if packets.shape[0] else None, packets.shape[0], packets.shape[1], mcnt0, n_blocks,
                 n_boards, n_chans, xid, index, out, stream)
     return out, index
+
+
+def xeng_channelise(adc, n_samples: int, n_inputs: int, n_chans: int, out, tables, stream=None) -> None:
+    s = getattr(stream, "cuda_stream", stream)
+    _check(_lib.xeng_channelise(_ptr(adc), n_samples, n_inputs, n_chans, _ptr(out), _ptr(tables), s))
+
+
+def channelise(adc, n_chans: int, out=None, tables=None, stream=None):
+    """F-stage channeliser: int8 CUDA tensor [N, n_samples] of ADC samples ->
+    complex64 spectra [S, F, N] (time, channel, input)."""
+    import torch
+    if adc.dim() != 2 or adc.dtype != torch.int8 or not adc.is_cuda or not adc.is_contiguous():
+        raise ValueError("adc must be a contiguous int8 CUDA tensor [n_inputs, n_samples]")
+    N, S_in = adc.shape
+    S = int(_lib.xeng_channelise_spectra(S_in, n_chans))
+    if S < 0:
+        raise ValueError("bad sizes")
+    if out is None:
+        out = torch.empty((S, n_chans, N), dtype=torch.complex64, device=adc.device)
+    if tables is None:
+        tables = torch.empty(int(_lib.xeng_channelise_table_floats(n_chans)), dtype=torch.float32,
+                             device=adc.device)
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    xeng_channelise(adc, S_in, N, n_chans, out, tables, stream)
+    return out
 
 
 # ------------------------------------------------------------ tensor wrapper

@@ -114,3 +114,16 @@ def test_ingest_argument_checks_without_device():
     assert call(mcnt0=1 << 48) == X.XENG_EINVAL
     assert call(pk=12) == X.XENG_EINVAL                           # misaligned packets
     assert call(blocks=65536) == X.XENG_EINVAL
+
+
+def test_channelise_sizes_and_checks_without_device():
+    from paper_1904_07778_amd import xeng as X
+    lib = X._lib
+    assert lib.xeng_channelise_spectra(2048 * 10, 1024) == 7
+    assert lib.xeng_channelise_spectra(2048 * 3, 1024) == 0
+    assert lib.xeng_channelise_table_floats(1024) == 4 * 2048 + 2048
+    assert lib.xeng_channelise(8, 2048, 3, 1024, 16, 16, None) == X.XENG_EINVAL   # odd input count
+    assert lib.xeng_channelise(8, 2048, 2, 1000, 16, 16, None) == X.XENG_EINVAL   # not a power of two
+    assert lib.xeng_channelise(8, 2048, 2, 2048, 16, 16, None) == X.XENG_EINVAL   # FFT too long
+    assert lib.xeng_channelise(8, 2044, 2, 1024, 16, 16, None) == X.XENG_EINVAL   # samples % 8
+    assert lib.xeng_channelise(8, 2048, 2, 1024, 24, 16, None) == X.XENG_EINVAL   # out misaligned
