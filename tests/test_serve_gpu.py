@@ -111,3 +111,41 @@ def test_lost_blocks_are_detected_and_skipped():
     check(srv, hosts, subs, drops=drops)
     lost = [d.lost_samples for d in sorted(srv.done, key=lambda d: d.index)]
     assert lost == [1024, 2048, 1024]
+
+
+def test_full_size_subarrays_sampled_channels():
+    """The streaming workload's four sub-arrays at full size (1024-sample
+    blocks from device rings, as the bench runs them), two of them waiting
+    for memory; each sub-array's dumps checked on sampled channels."""
+    import torch
+    from paper_1904_07778_amd.serve import BLOCK_T, Feed, Request, Server, drive
+    subs = synth.stream_subarrays()
+    ring = 2
+    reqs, feeds, hosts = [], {}, {}
+    for k, s in enumerate(subs):
+        n, f = s["n_inputs"], s["n_chans"]
+        dump_len = min(s["dump_len"], 4 * BLOCK_T)          # keep the oracle's share short
+        r = Request(f"{n}x{f}", n, f, dump_len, 2, ring_blocks=ring)
+        host = synth.voltages("sources", 5, n, f, ring * BLOCK_T, array=k, n_src=1)
+        hosts[r.name] = host
+        feeds[r.name] = Feed(torch.from_numpy(host).cuda(), 2 * dump_len // BLOCK_T)
+        reqs.append(r)
+    budget = reqs[0].footprint() + reqs[1].footprint()       # the two small ones wait
+    print("serve full size, budget", budget, flush=True)
+    srv = Server(budget)
+    drive(srv, [(0.0, r) for r in reqs], feeds, paced=False, time_limit=120)
+    srv.close()
+    for r in reqs:
+        mine = sorted([d for d in srv.done if d.name == r.name], key=lambda d: d.index)
+        assert [d.index for d in mine] == [0, 1]
+        chans = [0, r.n_chans // 2, r.n_chans - 1]
+        per = r.dump_len // BLOCK_T
+        for d in mine:
+            e = oracle.Engine(r.n_inputs, len(chans))
+            for seq in range(d.index * per, (d.index + 1) * per):
+                row = (seq % ring) * BLOCK_T
+                e.correlate(np.ascontiguousarray(hosts[r.name][row:row + BLOCK_T][:, chans]))
+            want = e.dump()[0]
+            got = d.vis.numpy()[chans]
+            assert d.n_integrated == r.dump_len
+            assert np.array_equal(got, want), f"{r.name} dump {d.index}: " + first_mismatch(got, want)
