@@ -138,6 +138,7 @@ def main() -> int:
                     choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant", "ingest", "chan"])
     ap.add_argument("--stream-dumps", type=int, default=4, help="dumps per request (stream, saturating)")
     ap.add_argument("--paced-seconds", type=float, default=6.0, help="length of the paced run (stream)")
+    ap.add_argument("--stream-ring", type=int, default=16, help="device ring depth in blocks per sub-array (stream)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -349,7 +350,7 @@ def bench_stream(args) -> int:
     from paper_1904_07778_amd.xeng import Plan
 
     subs = synth.stream_subarrays()
-    ring_blocks = 4
+    ring_blocks = args.stream_ring
     log(f"stream workload: {subs}")
     rings = {}
     for k, s in enumerate(subs):
@@ -431,8 +432,8 @@ def bench_stream(args) -> int:
                                     "blocks of 1024 samples, dump lengths "
                                     + "/".join(str(s["dump_len"]) for s in subs)
                                     + f", two waves of {args.stream_dumps} dumps each under a "
-                                      "budget that fits one wave; blocks pre-staged in HBM rings",
-                        "budget_bytes": budget})
+                                      f"budget that fits one wave; blocks pre-staged in HBM rings of {ring_blocks}",
+                        "budget_bytes": budget, "ring_blocks": ring_blocks})
     rec["steps"] = srv.iterations
     rec.update({
         "plain_value": cmac / t_plain, "speedup_vs_plain": t_plain / t_serve,
