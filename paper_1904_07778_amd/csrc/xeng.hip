@@ -280,6 +280,9 @@ int record_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_tim
 // refused); a graph is updated only after its previous launch has completed,
 // so a launch in flight never sees new parameters.
 int run_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_time) {
+  bool any = false;
+  for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) any = any || (p->arrays[a].active && n_time[a] > 0);
+  if (!any) return XENG_OK;  // nothing to launch
   const int slot = p->next_graph;
   p->next_graph = (slot + 1) % xeng_plan_s::GRAPH_RING;
   hipError_t e;

@@ -247,3 +247,24 @@ def test_batched_restart_after_dump_with_time_split():
     for (N, F, _), b, got in zip(shapes, b2, out):
         want = oracle_vis([b], N, F)
         assert np.array_equal(got.numpy(), want), f"N={N}: " + first_mismatch(got.numpy(), want)
+
+
+def test_batched_call_with_nothing_to_do():
+    """A batched call whose arrays all pass zero samples launches nothing and
+    changes nothing; the next real call still lands exactly."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    rng = np.random.default_rng(43)
+    shapes = [(32, 3, 512), (64, 2, 512)]
+    b = [rand_block(rng, 512, F, N) for N, F, _ in shapes]
+    print("batched empty call", flush=True)
+    with Plan(shapes) as p:
+        p.correlate([None, None])
+        _, n0 = p.dump(keep=True, to_host=True)
+        p.correlate([to_dev(x) for x in b])
+        p.correlate([None, None])
+        out, n = p.dump(to_host=True)
+    torch.cuda.synchronize()
+    assert list(n0) == [0, 0] and list(n) == [512, 512]
+    for (N, F, _), x, got in zip(shapes, b, out):
+        assert np.array_equal(got.numpy(), oracle_vis([x], N, F))
