@@ -24,7 +24,9 @@
  * All entry points return an xeng status (0 = OK, < 0 = error) unless stated;
  * no entry point throws or aborts.  Device pointers are HIP device memory of
  * the device current when the plan was made.  Every call on one plan must come
- * from one host thread at a time.
+ * from one host thread at a time.  With the environment variable XENG_TRACE
+ * set (not "0") when a plan is made, the plan logs every kernel launch to
+ * stderr.
  */
 #ifndef XENG_H
 #define XENG_H
@@ -152,6 +154,30 @@ int xeng_attach(xeng_plan_t *p, const xeng_array_desc *d, int32_t *index);
  * Errors: EINVAL (slot out of range or free), EDEVICE, ESTATE.
  */
 int xeng_detach(xeng_plan_t *p, int32_t index);
+
+/* Counters of a plan since it was made (xeng_stats). */
+typedef struct {
+    int64_t calls;      /* xeng_correlate calls that did work                     */
+    int64_t launches;   /* kernel launches (plain, or persistent batch launches)   */
+    int64_t samples;    /* time samples integrated, summed over arrays             */
+    int64_t cmacs;      /* useful complex MACs: samples x F x N(N+1)/2, summed     */
+    int64_t bytes_in;   /* voltage bytes consumed                                  */
+    int64_t dumps;      /* arrays dumped                                           */
+    int64_t bytes_out;  /* visibility bytes dumped                                 */
+} xeng_stats_t;
+
+/* Copy the plan's counters to out.  Errors: EINVAL (null pointers). */
+int xeng_stats(const xeng_plan_t *p, xeng_stats_t *out);
+
+/*
+ * xeng_load_acc - seed an array's integration from saved visibilities (resume
+ * from a checkpoint: the accumulator is the engine's whole state, and a KEEP
+ * dump is a snapshot of it).  src is int32 [F][N(N+1)/2][2], device or host
+ * memory (caller-owned, read on the plan's stream); n_integrated is the
+ * sample count it holds (0 .. XENG_MAX_INTEGRATION).  Later calls add to it.
+ * Errors: EINVAL, EDEVICE, ESTATE.
+ */
+int xeng_load_acc(xeng_plan_t *p, int32_t array, const int32_t *src, int64_t n_integrated);
 
 /* Number of slots of the plan (attached or free); -1 for NULL. */
 int32_t xeng_slots(const xeng_plan_t *p);

@@ -60,6 +60,8 @@ struct xeng_plan_s {
   hipGraphExec_t exec[GRAPH_RING] = {};
   hipEvent_t done[GRAPH_RING] = {};
   int next_graph = 0;
+  xeng_stats_t stats{};   // counters since the plan was made
+  bool trace = false;     // XENG_TRACE set: one stderr line per launch
   std::string err;
 };
 
@@ -172,6 +174,10 @@ int launch_plain(xeng_plan_t* p, ArrayState& s, const uint8_t* v, int64_t T) {
   xeng::Args args = base_args(s, v, T);
   dim3 grid;
   grid_for(p, s, T, grid, args.t_chunk, args.mode);
+  ++p->stats.launches;
+  if (p->trace)
+    fprintf(stderr, "xeng: plan %p plain launch N=%d F=%d T=%lld grid=%ux%u threads=%d mode=%d\n", (void*)p,
+            args.N, args.F, (long long)T, grid.x, grid.y, s.k->threads, args.mode);
   if (args.mode == xeng::EPI_ATOMIC && s.clean && !s.zeroed) {
     const int st = zero_fill(p, {&s});
     if (st != XENG_OK) return st;
@@ -264,6 +270,10 @@ int record_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_tim
       n_items += (int64_t)b.ngroups * b.nchunks;
     }
     const int grid = (int)std::min<int64_t>(p->n_cu, n_items);
+    ++p->stats.launches;
+    if (p->trace)
+      fprintf(stderr, "xeng: plan %p batch launch arrays=%d items=%lld grid=%d\n", (void*)p, bp.n_arrays,
+              (long long)n_items, grid);
     hipError_t e = xeng::batch::launch(grid, p->stream, bp);
     if (e != hipSuccess) return hip_fail(p, e, "batch kernel launch");
   }
@@ -371,11 +381,15 @@ int correlate_unchecked(xeng_plan_t* p, const uint8_t* const* d_voltages, const 
       if (st != XENG_OK) return st;
     }
   }
+  ++p->stats.calls;
   for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) {
     ArrayState& s = p->arrays[a];
     if (!s.active || n_time[a] == 0) continue;
     s.n_integrated += n_time[a];
     s.clean = s.zeroed = false;
+    p->stats.samples += n_time[a];
+    p->stats.cmacs += n_time[a] * (int64_t)s.d.n_chans * nbl_of(s.d.n_inputs);
+    p->stats.bytes_in += n_time[a] * (int64_t)s.d.n_chans * s.d.n_inputs;
   }
   return XENG_OK;
 }
@@ -428,6 +442,10 @@ int xeng_plan(xeng_plan_t** out, const xeng_array_desc* arrays, int32_t n_arrays
   xeng_plan_t* p = new (std::nothrow) xeng_plan_t();
   if (!p) return XENG_ENOMEM;
   p->batched = n_arrays > 1 || (flags & XENG_PLAN_BATCH);
+  {
+    const char* t = getenv("XENG_TRACE");
+    p->trace = t && *t && strcmp(t, "0") != 0;
+  }
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
@@ -647,6 +665,8 @@ int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags
       if (e != hipSuccess) return hip_fail(p, e, "dump copy");
     }
     if (n_integrated) n_integrated[a - a0] = s.n_integrated;
+    ++p->stats.dumps;
+    p->stats.bytes_out += (int64_t)s.acc_bytes;
     if (!keep) {
       s.n_integrated = 0;
       s.clean = true;
@@ -658,6 +678,29 @@ int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return hip_fail(p, e, "dump synchronize");
   }
+  return XENG_OK;
+}
+
+int xeng_stats(const xeng_plan_t* p, xeng_stats_t* out) {
+  if (!p || !out) return XENG_EINVAL;
+  *out = p->stats;
+  return XENG_OK;
+}
+
+int xeng_load_acc(xeng_plan_t* p, int32_t array, const int32_t* src, int64_t n_integrated) {
+  if (!p || !src) return XENG_EINVAL;
+  if (p->dead) return XENG_ESTATE;
+  if (array < 0 || array >= (int32_t)p->arrays.size() || !p->arrays[array].active)
+    return fail(p, XENG_EINVAL, "slot %d holds no array", array);
+  if (n_integrated < 0 || n_integrated > XENG_MAX_INTEGRATION)
+    return fail(p, XENG_EINVAL, "n_integrated %lld outside [0, %lld]", (long long)n_integrated,
+                (long long)XENG_MAX_INTEGRATION);
+  ArrayState& s = p->arrays[array];
+  hipError_t e = hipMemcpyAsync(s.acc, src, s.acc_bytes, hipMemcpyDefault, p->stream);
+  if (e != hipSuccess) return hip_fail(p, e, "accumulator load");
+  s.n_integrated = n_integrated;
+  s.clean = false;   // the next launch adds to the loaded sums
+  s.zeroed = false;
   return XENG_OK;
 }
 

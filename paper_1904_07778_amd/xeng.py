@@ -80,6 +80,17 @@ _lib.xeng_channelise_table_floats.argtypes = [ctypes.c_int32]
 _lib.xeng_channelise_table_floats.restype = ctypes.c_int64
 
 
+class xeng_stats_t(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("calls", "launches", "samples", "cmacs", "bytes_in", "dumps", "bytes_out")]
+
+
+_lib.xeng_stats.argtypes = [_P, ctypes.POINTER(xeng_stats_t)]
+_lib.xeng_stats.restype = ctypes.c_int
+_lib.xeng_load_acc.argtypes = [_P, ctypes.c_int32, _P, ctypes.c_int64]
+_lib.xeng_load_acc.restype = ctypes.c_int
+
+
 class XengError(RuntimeError):
     def __init__(self, status: int, msg: str = ""):
         self.status = status
@@ -182,6 +193,16 @@ def xeng_last_error(plan: int) -> str:
 
 def xeng_integrated(plan: int, array: int) -> int:
     return int(_lib.xeng_integrated(plan, array))
+
+
+def xeng_stats(plan: int) -> dict:
+    st = xeng_stats_t()
+    _check(_lib.xeng_stats(plan, ctypes.byref(st)), plan)
+    return {k: getattr(st, k) for k, _ in xeng_stats_t._fields_}
+
+
+def xeng_load_acc(plan: int, array: int, src, n_integrated: int) -> None:
+    _check(_lib.xeng_load_acc(plan, array, _ptr(src), n_integrated), plan)
 
 
 def xeng_requantize(words, gains, out, n_time: int, n_chans: int, n_inputs: int, stream=None) -> None:
@@ -382,6 +403,25 @@ class Plan:
         ptrs, ts = self._marshal(voltages)
         self.stream.wait_stream(torch.cuda.current_stream())
         return xeng_autotune(self.handle, ptrs, ts, reps)
+
+    def stats(self) -> dict:
+        """Counters since the plan was made (calls, launches, samples, cmacs,
+        bytes_in, dumps, bytes_out)."""
+        return xeng_stats(self.handle)
+
+    def load(self, array: int, vis, n_integrated: int) -> None:
+        """Seed an array's integration from saved visibilities (int32 [F, nbl, 2],
+        host or device), e.g. a KEEP dump taken earlier."""
+        import torch
+        s = self.specs[array]
+        if tuple(vis.shape) != (s.n_chans, s.nbl, 2) or vis.dtype != torch.int32 or not vis.is_contiguous():
+            raise ValueError("vis must be a contiguous int32 tensor [F, nbl, 2]")
+        self.stream.wait_stream(torch.cuda.current_stream())
+        xeng_load_acc(self.handle, array, vis, n_integrated)
+        if vis.is_cuda:
+            vis.record_stream(self.stream)
+        else:
+            self.stream.synchronize()   # the host buffer is read on the stream
 
     def new_output(self, array: int, host: bool = False):
         import torch

@@ -127,3 +127,10 @@ def test_channelise_sizes_and_checks_without_device():
     assert lib.xeng_channelise(8, 2048, 2, 2048, 16, 16, None) == X.XENG_EINVAL   # FFT too long
     assert lib.xeng_channelise(8, 2044, 2, 1024, 16, 16, None) == X.XENG_EINVAL   # samples % 8
     assert lib.xeng_channelise(8, 2048, 2, 1024, 24, 16, None) == X.XENG_EINVAL   # out misaligned
+
+
+def test_stats_and_load_argument_checks():
+    from paper_1904_07778_amd import xeng as X
+    lib = X._lib
+    assert lib.xeng_stats(None, None) == X.XENG_EINVAL
+    assert lib.xeng_load_acc(None, 0, None, 0) == X.XENG_EINVAL

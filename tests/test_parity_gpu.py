@@ -198,3 +198,43 @@ def test_restart_after_dump_every_epilogue(to_host):
         assert np.array_equal(got, want), first_mismatch(got, want)
     assert n2 == 0 and not g2.any()
     assert n3 == 1212
+
+
+def test_checkpoint_resume_and_counters():
+    """A KEEP dump is a snapshot; a new plan seeded with it (xeng_load_acc)
+    and fed the remaining blocks ends bit-identical to the uninterrupted run.
+    The plan counters add up."""
+    import subprocess
+    import sys
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    rng = np.random.default_rng(51)
+    N, F = 96, 5
+    blocks = [synth.pack(rng.integers(-8, 8, size=(t, F, N)), rng.integers(-8, 8, size=(t, F, N)))
+              for t in (700, 1200, 300)]
+    print("checkpoint / resume", flush=True)
+    with Plan([(N, F, 2000)]) as p:
+        for b in blocks:
+            p.correlate([torch.from_numpy(b).cuda()])
+        whole, n_whole = p.dump(to_host=True)
+        st = p.stats()
+    assert st["calls"] == 3 and st["samples"] == 2200 and st["dumps"] == 1
+    assert st["cmacs"] == 2200 * F * N * (N + 1) // 2 and st["bytes_in"] == 2200 * F * N
+    with Plan([(N, F, 2000)]) as p:
+        p.correlate([torch.from_numpy(blocks[0]).cuda()])
+        snap, n_snap = p.dump(keep=True, to_host=True)          # checkpoint
+    with Plan([(N, F, 2000)]) as q:
+        q.load(0, snap[0], n_snap[0])                           # resume from host memory
+        for b in blocks[1:]:
+            q.correlate([torch.from_numpy(b).cuda()])
+        resumed, n_res = q.dump(to_host=True)
+    torch.cuda.synchronize()
+    assert n_res[0] == n_whole[0] == 2200
+    assert np.array_equal(resumed[0].numpy(), whole[0].numpy())
+    # the launch trace goes to stderr when XENG_TRACE is set
+    code = ("import torch, numpy as np; from paper_1904_07778_amd.xeng import Plan\n"
+            "p = Plan([(32, 2, 64)]); p.correlate([torch.zeros((64, 2, 32), dtype=torch.uint8, device='cuda')]);"
+            " torch.cuda.synchronize(); p.close()")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120,
+                       env={**__import__("os").environ, "XENG_TRACE": "1"})
+    assert r.returncode == 0 and "plain launch N=32 F=2 T=64" in r.stderr, r.stderr[-500:]
