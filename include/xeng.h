@@ -43,7 +43,7 @@ typedef struct xeng_plan_s xeng_plan_t;
  * time samples one xeng_correlate call may pass for it. */
 typedef struct {
     int32_t n_inputs;           /* N, 1 .. XENG_MAX_INPUTS              */
-    int32_t n_chans;            /* F, >= 1                              */
+    int32_t n_chans;            /* F, >= 1, F * N <= 2^31 - 1           */
     int64_t max_time_per_call;  /* >= 1, <= XENG_MAX_INTEGRATION        */
 } xeng_array_desc;
 

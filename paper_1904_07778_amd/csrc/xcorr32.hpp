@@ -50,6 +50,7 @@ namespace x32 {
 constexpr int STAGE_T = 64;           // time samples per ring stage
 constexpr int MAX_T_PER_WG = 32768;   // int32 headroom of the x256 sums
 constexpr int MAX_UNITS_PER_WAVE = 11;
+constexpr bool DMA_STAGGER = false;
 
 template <int B, int E, typename F>
 __device__ __forceinline__ void sfor(F&& f) {
@@ -226,10 +227,17 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   const int64_t row_stride = (int64_t)a.F * N;
   const int nch_valid = min(CPW, a.F - f0);  // the last group may be short of channels
 
-  // ---- producer: wave-wide loads q = wave, wave + WAVES, ... of every stage
+  // ---- producer: wave-wide loads q = wave, wave + WAVES, ... of every stage.
+  // Each lane keeps the source address of its 16 bytes in stage 0 (time row
+  // src_t of the stage); stage st moves it by min(64 st, nt - 1 - src_t) rows,
+  // which clamps the rows past the end of the range to the last valid row
+  // (zeroed later by the reader) with one min and one multiply-add per load.
   const int my_loads = (C::LOADS - wave + C::WAVES - 1) / C::WAVES;
-  int64_t src_off[C::LPW_MAX];
-  int src_t[C::LPW_MAX];
+  // with one channel per workgroup the wave index is WC and known here
+  const bool extra_load = CPW == 1 ? (WC + C::LPW_MIN * C::WAVES < C::LOADS)
+                                   : (wave + C::LPW_MIN * C::WAVES < C::LOADS);
+  const uint8_t* src[C::LPW_MAX];
+  int src_last[C::LPW_MAX];  // nt - 1 - src_t: the largest row offset this lane may take
 #pragma unroll
   for (int k = 0; k < C::LPW_MAX; ++k) {
     const int q = wave + k * C::WAVES;
@@ -240,21 +248,27 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
     int ch = p / (N / 16);
     const int kc = p % (N / 16);
     if (ch >= nch_valid) ch = nch_valid - 1;              // channels past F: dropped later
-    src_t[k] = t;
-    src_off[k] = (int64_t)(f0 + ch) * N + 16 * kc;
+    src_last[k] = nt - 1 - t;
+    src[k] = a.v + (t_begin + t) * row_stride + (int64_t)(f0 + ch) * N + 16 * kc;
   }
-  auto issue_stage = [&](int st) {
-    const uint32_t base = lds_addr(lds) + (uint32_t)((st % S) * C::STAGE_BYTES);
-    const int64_t tb = t_begin + (int64_t)st * STAGE_T;
+  const uint32_t ring_base = __builtin_amdgcn_readfirstlane(lds_addr(lds));
+  // Addresses of the loads of stage st (computed ahead of their issue).
+  const int rs32 = (int)row_stride;  // F N < 2^31 (checked by the host)
+  auto stage_src = [&](int st, const uint8_t* (&g)[C::LPW_MAX]) {
 #pragma unroll
-    for (int k = 0; k < C::LPW_MAX; ++k) {
-      const int q = wave + k * C::WAVES;
-      if (q < C::LOADS) {
-        int64_t tt = tb + src_t[k];
-        if (tt >= t_end) tt = t_end - 1;  // tail rows: valid bytes, zeroed by the reader
-        lds_dma16(a.v + tt * row_stride + src_off[k], __builtin_amdgcn_readfirstlane(base + q * 1024));
-      }
-    }
+    for (int k = 0; k < C::LPW_MAX; ++k)
+      g[k] = src[k] + (int64_t)min(st * STAGE_T, src_last[k]) * (int64_t)rs32;
+  };
+  auto issue_loads = [&](int st, const uint8_t* const (&g)[C::LPW_MAX]) {
+    const uint32_t base = ring_base + (uint32_t)((st % S) * C::STAGE_BYTES);
+#pragma unroll
+    for (int k = 0; k < C::LPW_MAX; ++k)
+      if (k < C::LPW_MIN || extra_load) lds_dma16(g[k], base + (wave + k * C::WAVES) * 1024);
+  };
+  auto issue_stage = [&](int st) {
+    const uint8_t* g[C::LPW_MAX];
+    stage_src(st, g);
+    issue_loads(st, g);
   };
 
   // ---- consumer
@@ -295,7 +309,6 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
         *reinterpret_cast<v4i*>(slot + 16 * i) = v4i{0, 0, 0, 0};
       __syncthreads();
     }
-    if (st + S - 1 < nstages) issue_stage(st + S - 1);
   };
 
   // Transposed reads of the raw bytes of K-step ks of stage st (tile X, K-half h).
@@ -344,10 +357,14 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   // issues the transposed reads of step k+2, unpacks step k+1 (read one
   // block earlier, so already in registers) and runs step k's MFMAs; the
   // three parts are independent and the scheduling groups interleave the
-  // unpack VALU with the MFMAs.  Blocks hold no branches: the stage entry
-  // (waits, barrier, DMA issue) sits between blocks and the last stage is
-  // peeled off.  Samples past the end of the range are zero (enter_stage),
-  // so whole K-steps are run.
+  // unpack VALU with the MFMAs.  A block runs as two halves (K-half h = 0,
+  // then 1: its unpack and its MFMAs); the ring loads of a later stage are
+  // issued between the halves of one block of the stage, with their
+  // addresses computed in the first half, so that their issue overlaps
+  // running MFMAs instead of the stage barrier.  The stage entry (waits,
+  // barrier) sits between blocks and the last stage is peeled off.  Samples
+  // past the end of the range are zero (enter_stage), so whole K-steps are
+  // run.
   static_assert(STAGE_T == 64, "two K-steps per stage");
   constexpr int NTILE = [] {
     int n = 0;
@@ -355,35 +372,86 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
     return n;
   }();
   constexpr int NREAD = 2 * NTILE;
-  constexpr int NMFMA = 2 * NU;
-  constexpr int VPM = (6 * NREAD + NMFMA - 1) / NMFMA + 1;  // VALU slots per MFMA
-  auto interleave = [&]() {
-    __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);  // transposed reads first
-    sfor<0, NMFMA>([&](auto) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // one MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, VPM, 0);  // then unpack VALU
+  constexpr int VPH = (3 * NREAD + 2 * C::LPW_MAX + NU - 1) / NU + 1;  // VALU slots per MFMA
+  // scheduling groups of one half block: (the reads,) then MFMA / VALU pairs
+  auto interleave_half = [&](auto with_reads) {
+    if constexpr (with_reads.value) __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
+    sfor<0, NU>([&](auto) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, VPH, 0);
     });
   };
+  auto unpack_h = [&](auto h, const v2i (&raw)[NT][2], v4i (&P)[NT][2]) {
+    sfor<0, NT>([&](auto X) {
+      if constexpr (plan.needP[WC][X]) {
+        uint32_t w0 = (uint32_t)raw[X][h][0], w1 = (uint32_t)raw[X][h][1];
+        if constexpr (N % 32 == 16 && X == NT - 1) {
+          if (upper_pad) w0 = w1 = 0u;
+        }
+        P[X][h] = v4i{(int)(w0 & 0xF0F0F0F0u), (int)(w1 & 0xF0F0F0F0u),
+                      (int)((w0 << 4) & 0xF0F0F0F0u), (int)((w1 << 4) & 0xF0F0F0F0u)};
+      }
+    });
+  };
+  auto mfma_h = [&](auto h, const v4i (&P)[NT][2]) {
+    sfor<0, NU>([&](auto u) {
+      constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u];
+      if constexpr (plan.uIm[WC][u]) {
+        const v4i q = v4i{P[I][h][2], P[I][h][3], ~P[I][h][0], ~P[I][h][1]};
+        acc[u] = mfma32(q, P[J][h], acc[u]);
+      } else {
+        acc[u] = mfma32(P[I][h], P[J][h], acc[u]);
+      }
+    });
+  };
+  // One block: reads of (st_rd, ks_rd), unpack of raw_up into P_up, MFMAs on
+  // P_mm; with `loads` the loads of stage load_st go out mid-block.
+  auto block = [&](auto loads, int st_rd, int ks_rd, v2i (&raw_rd)[NT][2], const v2i (&raw_up)[NT][2],
+                   v4i (&P_up)[NT][2], const v4i (&P_mm)[NT][2], int load_st) {
+    read_step(st_rd, ks_rd, raw_rd);
+    const uint8_t* g[C::LPW_MAX];
+    if constexpr (loads.value) stage_src(load_st, g);
+    unpack_h(std::integral_constant<int, 0>{}, raw_up, P_up);
+    mfma_h(std::integral_constant<int, 0>{}, P_mm);
+    interleave_half(std::true_type{});
+    if constexpr (loads.value) {
+      __builtin_amdgcn_sched_barrier(0);
+      issue_loads(load_st, g);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    unpack_h(std::integral_constant<int, 1>{}, raw_up, P_up);
+    mfma_h(std::integral_constant<int, 1>{}, P_mm);
+    interleave_half(std::false_type{});
+  };
+  // which block of a stage issues this wave's loads: alternate by wave so
+  // that the workgroup's loads are spread over the stage
+  constexpr int LOAD_BLOCK = DMA_STAGGER ? (WC & 1) : 0;
   v4i P0[NT][2], P1[NT][2];
   v2i rawE[NT][2], rawO[NT][2];  // raw bytes of the even / odd K-step of a stage
   enter_stage(0);
+  if (S - 1 < nstages) issue_stage(S - 1);
   read_step(0, 0, rawE);
   read_step(0, 1, rawO);
   unpack(rawE, P0);
-  for (int st = 0; st + 1 < nstages; ++st) {
+  using LoadsFirst = std::bool_constant<LOAD_BLOCK == 0>;
+  using LoadsSecond = std::bool_constant<LOAD_BLOCK == 1>;
+  int st = 0;
+  for (; st + S < nstages; ++st) {  // stage st + S is still to be loaded
     enter_stage(st + 1);
-    read_step(st + 1, 0, rawE);
-    unpack(rawO, P1);
-    mfma_step(P0);
-    interleave();
-    read_step(st + 1, 1, rawO);
-    unpack(rawE, P0);
-    mfma_step(P1);
-    interleave();
+    block(LoadsFirst{}, st + 1, 0, rawE, rawO, P1, P0, st + S);
+    block(LoadsSecond{}, st + 1, 1, rawO, rawE, P0, P1, st + S);
   }
-  unpack(rawO, P1);
-  mfma_step(P0);
-  interleave();
+  for (; st + 1 < nstages; ++st) {
+    enter_stage(st + 1);
+    block(std::false_type{}, st + 1, 0, rawE, rawO, P1, P0, 0);
+    block(std::false_type{}, st + 1, 1, rawO, rawE, P0, P1, 0);
+  }
+  unpack_h(std::integral_constant<int, 0>{}, rawO, P1);
+  mfma_h(std::integral_constant<int, 0>{}, P0);
+  interleave_half(std::false_type{});
+  unpack_h(std::integral_constant<int, 1>{}, rawO, P1);
+  mfma_h(std::integral_constant<int, 1>{}, P0);
+  interleave_half(std::false_type{});
   mfma_step(P1);
   mfma_drain();
 

@@ -107,6 +107,7 @@ void grid_for(const xeng_plan_t* p, const ArrayState& s, int64_t T, dim3& grid, 
 
 bool valid_desc(const xeng_array_desc& d) {
   return d.n_inputs >= 1 && d.n_inputs <= XENG_MAX_INPUTS && d.n_chans >= 1 &&
+         (int64_t)d.n_chans * d.n_inputs <= INT32_MAX &&  // one time row indexes in 32 bits
          d.max_time_per_call >= 1 && d.max_time_per_call <= XENG_MAX_INTEGRATION;
 }
 
