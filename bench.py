@@ -6,9 +6,12 @@ feeds, paper Sec. 1) with a 1024-point spectrum (Sec. 2.1), 8192 spectra per
 integration, 4+4-bit seeded synthetic voltages (quantised Gaussian sigma 2.5
 plus three correlated point sources), resident in HBM before timing.
 
-One step = one pass of the plain engine over one integration:
-xeng_correlate (stage, unpack, int8 MFMA contraction, integrate into the
-HBM accumulator) + xeng_dump to a device buffer (copy out, clear).
+One step = one pass of the plain engine over one integration, delivered
+into a device buffer: xeng_correlate_dump (stage, unpack, int8 MFMA
+contraction, integrate, with the epilogue writing the visibilities straight
+into the caller's buffer).  The same step as separate xeng_correlate (into
+the HBM accumulator) + xeng_dump (copy out) calls is timed after it and
+reported as ms_per_step_separate_calls.
 
 Printed: one JSON line with the useful complex-MAC rate of the step
 (N(N+1)/2 * F * T per step, Hermitian triangle with autos), its real-time
@@ -18,11 +21,11 @@ events on the engine's stream) and the CPU oracle timed on a bounded sample
 of the same workload.
 
 Other workloads (one JSON line each, same keys plus a comparison):
-  --workload batch    12 arrays of uneven N, F, T (seeded): one batched call
-                      (persistent launch in a captured graph) + one dump per
-                      step, against 12 plain correlate + dump calls on the
-                      same stream; both autotuned first; outputs compared
-                      bit for bit.
+  --workload batch    12 arrays of uneven N, F, T (seeded): one batched
+                      correlate-and-dump call (persistent launch in a captured
+                      graph) per step, against 12 plain correlate-and-dump
+                      calls on the same stream; both autotuned first; outputs
+                      compared bit for bit.
   --workload requant  the F stage's equaliser / 4-bit requantiser at the
                       cylinder shape (PFB words [8192][1024][192] -> packed
                       bytes), HBM-bound: samples/s and GB/s against 8 TB/s.
@@ -132,8 +135,8 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5) -> None:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="cylinder",
                     choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant", "ingest", "chan"])
     ap.add_argument("--stream-dumps", type=int, default=4, help="dumps per request (stream, saturating)")
@@ -189,7 +192,12 @@ def main() -> int:
     out = plan.new_output(0)
     torch.cuda.synchronize()
 
+    # A step is one integration of T samples delivered into `out`: the fused
+    # call (the kernel writes the visibilities straight into `out`).  The
+    # separate correlate + dump calls (accumulator, then a copy) are timed
+    # after it for comparison.
     for _ in range(args.warmup):
+        plan.correlate_dump([v], out=[out])
         plan.correlate([v])
         plan.dump(0, out=[out])
     torch.cuda.synchronize()
@@ -201,13 +209,21 @@ def main() -> int:
     t_start = time.perf_counter()
     for k in range(args.steps):
         ev0[k].record(stream)
-        plan.correlate([v])
+        plan.correlate_dump([v], out=[out])
         ev1[k].record(stream)
-        plan.dump(0, out=[out])
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     log(f"timed {args.steps} steps in {t_total:.3f} s")
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
+
+    torch.cuda.synchronize()
+    t_sep = time.perf_counter()
+    for k in range(args.steps):
+        plan.correlate([v])
+        plan.dump(0, out=[out])
+    torch.cuda.synchronize()
+    ms_separate = 1e3 * (time.perf_counter() - t_sep) / args.steps
+    log(f"separate correlate + dump: {ms_separate:.4f} ms per step")
 
     ms_per_step = 1e3 * t_total / args.steps
     cmac_per_step = nbl * F * T
@@ -237,7 +253,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: N={N} inputs, F={F} channels, "
                                f"T={T} samples per integration, 4+4-bit complex",
-                   "n_inputs": N, "n_chans": F, "n_time": T, "step": "correlate + dump"},
+                   "n_inputs": N, "n_chans": F, "n_time": T,
+                   "step": "correlate + dump in one call (xeng_correlate_dump)"},
+        "ms_per_step_separate_calls": ms_separate,
         "int8_mfma_frac_of_step": value * OPS_PER_CMAC / (PEAK_INT8_TOPS * 1e12),
         "rtf": value / (nbl * REALTIME_SPECTRA_PER_S),
         "rtf_full_matrix_reading": value / (nbl * REALTIME_SPECTRA_PER_S) / 2,
@@ -288,14 +306,13 @@ def bench_batch(args) -> int:
     out_b = [batched.new_output(k) for k in range(len(shapes))]
     out_p = [p.new_output(0) for p in plain]
 
+    # both forms integrate and dump in one call per plan (xeng_correlate_dump)
     def step_batched():
-        batched.correlate(dev)
-        batched.dump(-1, out=out_b)
+        batched.correlate_dump(dev, out=out_b)
 
     def step_plain():
         for p, v, o in zip(plain, dev, out_p):
-            p.correlate([v])
-            p.dump(0, out=[o])
+            p.correlate_dump([v], out=[o])
 
     def timed(step):
         for _ in range(args.warmup):
@@ -318,7 +335,8 @@ def bench_batch(args) -> int:
                        cmac / (ms_b / 1e3), ms_b,
                        {"workload": "batch: 12 arrays, N in {16..192}, F in {256, 512, 1024}, "
                                     "T in {2048, 4096, 8192} (seed 4), 4+4-bit complex",
-                        "arrays": shapes, "step": "batched correlate + dump of all arrays"})
+                        "arrays": shapes,
+                        "step": "batched correlate + dump of all arrays in one call (xeng_correlate_dump)"})
     rec.update({
         "plain_value": cmac / (ms_p / 1e3), "plain_ms_per_step": ms_p,
         "speedup_vs_plain": ms_p / ms_b, "identical_to_plain": same,

@@ -137,6 +137,28 @@ int xeng_dump(xeng_plan_t *p, int32_t array, int32_t *const *dst, uint32_t flags
               int64_t *n_integrated);
 
 /*
+ * xeng_correlate_dump - integrate one block per array and dump it in the same
+ * call (the usual pattern of a correlator: one dump per integration, Sec. 2.2).
+ * Same result as xeng_correlate followed by xeng_dump of the arrays given a
+ * destination, but the kernels write the visibilities straight into the
+ * destination: an empty integration never touches the accumulator, and one
+ * with earlier samples has them copied over first.
+ *   d_voltages, n_time  as for xeng_correlate.
+ *   d_dst         one pointer per slot: NULL leaves that array integrating
+ *                 (as xeng_correlate); otherwise int32 [F][N(N+1)/2][2] device
+ *                 memory (checked), 8-byte aligned, caller-owned, receives the
+ *                 visibilities including this call's samples, and the
+ *                 array's integration restarts.  A slot with n_time 0 and a
+ *                 destination is dumped as by xeng_dump.
+ *   n_integrated  optional out, one per slot: samples in each dump (written
+ *                 for the dumped slots only).
+ * Asynchronous on the plan's stream.  Errors: as xeng_correlate, and EINVAL
+ * for a destination that is misaligned or not device memory.
+ */
+int xeng_correlate_dump(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64_t *n_time,
+                        int32_t *const *d_dst, int64_t *n_integrated);
+
+/*
  * xeng_attach - add an array to a batched plan between calls (admission of a
  * new sub-array into a running serving loop).
  *   d      its descriptor (read during the call only).

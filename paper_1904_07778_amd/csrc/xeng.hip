@@ -526,6 +526,86 @@ int xeng_correlate(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64
   return correlate_unchecked(p, d_voltages, n_time);
 }
 
+int xeng_correlate_dump(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_t* n_time,
+                        int32_t* const* d_dst, int64_t* n_integrated) {
+  if (!p || !n_time || !d_dst) return XENG_EINVAL;
+  if (p->dead) return XENG_ESTATE;
+  int st = validate_call(p, d_voltages, n_time);
+  if (st != XENG_OK) return st;
+  const int32_t na = (int32_t)p->arrays.size();
+  for (int32_t a = 0; a < na; ++a) {
+    if (!p->arrays[a].active || !d_dst[a]) continue;
+    if ((reinterpret_cast<uintptr_t>(d_dst[a]) & 7u) != 0)
+      return fail(p, XENG_EINVAL, "array %d: destination not 8-byte aligned", a);
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, d_dst[a]) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+      (void)hipGetLastError();
+      return fail(p, XENG_EINVAL, "array %d: destination is not device memory", a);
+    }
+  }
+  // Arrays dumped without new samples: a plain dump each.
+  for (int32_t a = 0; a < na; ++a) {
+    if (!p->arrays[a].active || !d_dst[a] || n_time[a] != 0) continue;
+    int32_t* dst[1] = {d_dst[a]};
+    st = xeng_dump(p, a, dst, 0, n_integrated ? n_integrated + a : nullptr);
+    if (st != XENG_OK) return st;
+  }
+  // The others integrate straight into their destination: an empty
+  // integration starts there from nothing (plain stores, or atomic adds into
+  // zeroed memory); earlier samples are copied over first and added to.
+  struct Saved {
+    int32_t a;
+    int32_t* acc;
+    bool clean, zeroed;
+    int64_t n;
+  };
+  std::vector<Saved> redirected;
+  xeng::DumpParams dp{};
+  int64_t most = 0;
+  for (int32_t a = 0; a < na; ++a) {
+    ArrayState& s = p->arrays[a];
+    if (!s.active || !d_dst[a] || n_time[a] == 0) continue;
+    redirected.push_back(Saved{a, s.acc, s.clean, s.zeroed, s.n_integrated});
+    if (!s.clean) {
+      if (dp.count == xeng::DUMP_MAX) return fail(p, XENG_EINVAL, "more than %d arrays to carry over", xeng::DUMP_MAX);
+      dp.acc[dp.count] = reinterpret_cast<const int2*>(s.acc);
+      dp.dst[dp.count] = reinterpret_cast<int2*>(d_dst[a]);
+      dp.n[dp.count] = (int64_t)(s.acc_bytes / sizeof(int2));
+      most = std::max(most, dp.n[dp.count]);
+      ++dp.count;
+    }
+  }
+  if (dp.count > 0) {
+    const int64_t blocks = std::min<int64_t>((most + 1023) / 1024, 8LL * p->n_cu);
+    hipError_t e = xeng::dump_launch((int)std::max<int64_t>(1, blocks), p->stream, dp);
+    if (e != hipSuccess) return hip_fail(p, e, "carry-over copy");
+  }
+  for (const Saved& r : redirected) {
+    ArrayState& s = p->arrays[r.a];
+    s.acc = d_dst[r.a];
+    s.zeroed = false;  // clean (empty) destinations hold unknown values
+  }
+  st = correlate_unchecked(p, d_voltages, n_time);
+  for (const Saved& r : redirected) {
+    ArrayState& s = p->arrays[r.a];
+    s.acc = r.acc;
+    if (st != XENG_OK) {
+      s.clean = r.clean;
+      s.zeroed = r.zeroed;
+      s.n_integrated = r.n;
+      continue;
+    }
+    if (n_integrated) n_integrated[r.a] = r.n + n_time[r.a];
+    ++p->stats.dumps;
+    p->stats.bytes_out += (int64_t)s.acc_bytes;
+    // the integration restarts; an accumulator that was empty was not written
+    s.n_integrated = 0;
+    s.clean = true;
+    s.zeroed = r.clean && r.zeroed;
+  }
+  return st;
+}
+
 int xeng_autotune(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_t* n_time,
                   int32_t reps, float* best_ms) {
   if (!p || !n_time || reps < 1) return XENG_EINVAL;

@@ -249,23 +249,47 @@ class Server:
                 nbl = s.req.n_inputs * (s.req.n_inputs + 1) // 2
                 self.cmac += nbl * s.req.n_chans * d.shape[0]
                 issued = True
+        fused = {}
         if issued:
-            self.plan.correlate(volts)
+            # slots whose integration this block completes are integrated and
+            # dumped in the same call, straight into their output buffer
+            ending = [s for s in self.slots.values()
+                      if volts[s.slot] is not None and s.covered >= s.req.dump_len]
+            for s in ending:
+                if self.keep_results:
+                    self._collect_older(s)
+            if ending:
+                outs = [None] * n_slots
+                for s in ending:
+                    outs[s.slot] = self.plan.new_output(s.slot)
+                outs, n = self.plan.correlate_dump(volts, out=outs)
+                fused = {s.slot: (outs[s.slot], n[s.slot]) for s in ending}
+            else:
+                self.plan.correlate(volts)
             self.iterations += 1
         for name in list(self.slots):
             s = self.slots[name]
             if s.covered >= s.req.dump_len:
-                self._dump(s)
+                self._dump(s, fused.get(s.slot))
         return issued
 
-    def _dump(self, s: _Slot) -> None:
+    def _collect_older(self, s: _Slot) -> None:
+        """The pinned buffer of dump k-2 is reused by dump k: collect that dump."""
+        k = s.dumps_done
+        for item in [i for i in self.pending if i.name == s.req.name and i.index == k - 2]:
+            self._finish(item, wait=True)
+
+    def _dump(self, s: _Slot, done=None) -> None:
+        """Hand dump k of slot s to the copy stream; `done` = (device output,
+        samples) when the correlate call already dumped it."""
         torch = self.torch
         k = s.dumps_done
         if self.keep_results:
-            # the pinned buffer of dump k-2 is reused: collect that dump first
-            for item in [i for i in self.pending if i.name == s.req.name and i.index == k - 2]:
-                self._finish(item, wait=True)
-        out, n = self.plan.dump(s.slot)                      # dump kernel, device buffer
+            self._collect_older(s)
+        if done is None:
+            out, n = self.plan.dump(s.slot)                  # dump kernel, device buffer
+        else:
+            out, n = [done[0]], [done[1]]
         dev_ev = torch.cuda.Event()
         dev_ev.record(self.plan.stream)
         host = s.host_bufs[k % 2]

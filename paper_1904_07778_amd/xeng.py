@@ -85,6 +85,9 @@ class xeng_stats_t(ctypes.Structure):
                 ("calls", "launches", "samples", "cmacs", "bytes_in", "dumps", "bytes_out")]
 
 
+_lib.xeng_correlate_dump.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_int64)]
+_lib.xeng_correlate_dump.restype = ctypes.c_int
 _lib.xeng_stats.argtypes = [_P, ctypes.POINTER(xeng_stats_t)]
 _lib.xeng_stats.restype = ctypes.c_int
 _lib.xeng_load_acc.argtypes = [_P, ctypes.c_int32, _P, ctypes.c_int64]
@@ -140,6 +143,16 @@ def xeng_dump(plan: int, array: int, dst: Sequence, flags: int = 0) -> list[int]
     ptrs = (_P * n)(*[_ptr(d) for d in dst])
     nint = (ctypes.c_int64 * n)()
     _check(_lib.xeng_dump(plan, array, ptrs, flags, nint), plan)
+    return list(nint)
+
+
+def xeng_correlate_dump(plan: int, voltages: Sequence, n_time: Sequence[int], dst: Sequence) -> list[int]:
+    n = len(n_time)
+    ptrs = (_P * n)(*[_ptr(v) for v in voltages])
+    ts = (ctypes.c_int64 * n)(*n_time)
+    outs = (_P * n)(*[_ptr(d) for d in dst])
+    nint = (ctypes.c_int64 * n)()
+    _check(_lib.xeng_correlate_dump(plan, ptrs, ts, outs, nint), plan)
     return list(nint)
 
 
@@ -395,6 +408,29 @@ class Plan:
             if v is not None:
                 v.record_stream(self.stream)
         xeng_correlate(self.handle, ptrs, ts)
+
+    def correlate_dump(self, voltages, out=None):
+        """Integrate one block per slot and dump every slot given a block into
+        out (device int32 [F, nbl, 2] tensors, made if None); returns (out,
+        n_integrated) like dump().  Slots whose voltage entry is None keep
+        integrating and get None in out."""
+        import torch
+        ptrs, ts = self._marshal(voltages)
+        if out is None:
+            out = [None if v is None else self.new_output(a) for a, v in enumerate(voltages)]
+        for a, (o, s) in enumerate(zip(out, self.specs)):
+            if o is None:
+                continue
+            if (not o.is_cuda or o.dtype != torch.int32 or not o.is_contiguous()
+                    or tuple(o.shape) != (s.n_chans, s.nbl, 2)):
+                raise ValueError(f"out[{a}] must be a contiguous int32 CUDA tensor [F, nbl, 2]")
+        self.stream.wait_stream(torch.cuda.current_stream())
+        for v in ptrs:
+            if v is not None:
+                v.record_stream(self.stream)
+        n = xeng_correlate_dump(self.handle, ptrs, ts, out)
+        torch.cuda.current_stream().wait_stream(self.stream)
+        return out, n
 
     def autotune(self, voltages, reps: int = 3) -> float:
         """Pick launch shapes by timing them on these inputs (accumulators must

@@ -134,3 +134,8 @@ def test_stats_and_load_argument_checks():
     lib = X._lib
     assert lib.xeng_stats(None, None) == X.XENG_EINVAL
     assert lib.xeng_load_acc(None, 0, None, 0) == X.XENG_EINVAL
+
+
+def test_correlate_dump_argument_checks():
+    from paper_1904_07778_amd import xeng as X
+    assert X._lib.xeng_correlate_dump(None, None, None, None, None) == X.XENG_EINVAL
