@@ -37,6 +37,7 @@ namespace xeng {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v6i __attribute__((ext_vector_type(6)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int KS = 32;  // time samples per MFMA K step (64 int8 = 32 x (re, im))

@@ -324,35 +324,6 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
       }
     });
   };
-  // Unpack raw bytes into MFMA operands (x16 scaled re | im).
-  auto unpack = [&](const v2i (&raw)[NT][2], v4i (&P)[NT][2]) {
-    sfor<0, NT>([&](auto X) {
-      if constexpr (plan.needP[WC][X]) {
-        sfor<0, 2>([&](auto h) {
-          uint32_t w0 = (uint32_t)raw[X][h][0], w1 = (uint32_t)raw[X][h][1];
-          if constexpr (N % 32 == 16 && X == NT - 1) {
-            if (upper_pad) w0 = w1 = 0u;
-          }
-          P[X][h] = v4i{(int)(w0 & 0xF0F0F0F0u), (int)(w1 & 0xF0F0F0F0u),
-                        (int)((w0 << 4) & 0xF0F0F0F0u), (int)((w1 << 4) & 0xF0F0F0F0u)};
-        });
-      }
-    });
-  };
-  auto mfma_step = [&](const v4i (&P)[NT][2]) {
-    sfor<0, 2>([&](auto h) {
-      sfor<0, NU>([&](auto u) {
-        constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u];
-        if constexpr (plan.uIm[WC][u]) {
-          const v4i q = v4i{P[I][h][2], P[I][h][3], ~P[I][h][0], ~P[I][h][1]};
-          acc[u] = mfma32(q, P[J][h], acc[u]);
-        } else {
-          acc[u] = mfma32(P[I][h], P[J][h], acc[u]);
-        }
-      });
-    });
-  };
-
   // Three-deep software pipeline over K-steps k (two per stage).  Block k
   // issues the transposed reads of step k+2, unpacks step k+1 (read one
   // block earlier, so already in registers) and runs step k's MFMAs; the
@@ -372,7 +343,14 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
     return n;
   }();
   constexpr int NREAD = 2 * NTILE;
-  constexpr int VPH = (3 * NREAD + 2 * C::LPW_MAX + NU - 1) / NU + 1;  // VALU slots per MFMA
+  constexpr int NQ = [] {
+    int n = 0;
+    for (int x = 0; x < NT; ++x) n += plan.needQ[WC][x] ? 1 : 0;
+    return n;
+  }();
+  // VALU slots per MFMA in a half block: 6 (+2) unpack operations per tile,
+  // and the load addresses
+  constexpr int VPH = (3 * NREAD + 2 * NQ + 2 * C::LPW_MAX + NU - 1) / NU + 1;
   // scheduling groups of one half block: (the reads,) then MFMA / VALU pairs
   auto interleave_half = [&](auto with_reads) {
     if constexpr (with_reads.value) __builtin_amdgcn_sched_group_barrier(0x100, NREAD, 0);
@@ -381,33 +359,41 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
       __builtin_amdgcn_sched_group_barrier(0x002, VPH, 0);
     });
   };
-  auto unpack_h = [&](auto h, const v2i (&raw)[NT][2], v4i (&P)[NT][2]) {
+  // Unpack the raw bytes of K-half h into MFMA operands, x16 scaled: six
+  // registers [re16 | im16 | ~re16] per tile, so that P = elements 0..3 and
+  // Q = elements 2..5 are both register windows of one tuple (no copies);
+  // tiles that are never the row of an imaginary product skip ~re16.
+  auto unpack_h = [&](auto h, const v2i (&raw)[NT][2], v6i (&P)[NT][2]) {
     sfor<0, NT>([&](auto X) {
       if constexpr (plan.needP[WC][X]) {
         uint32_t w0 = (uint32_t)raw[X][h][0], w1 = (uint32_t)raw[X][h][1];
         if constexpr (N % 32 == 16 && X == NT - 1) {
           if (upper_pad) w0 = w1 = 0u;
         }
-        P[X][h] = v4i{(int)(w0 & 0xF0F0F0F0u), (int)(w1 & 0xF0F0F0F0u),
-                      (int)((w0 << 4) & 0xF0F0F0F0u), (int)((w1 << 4) & 0xF0F0F0F0u)};
+        const int r0 = (int)(w0 & 0xF0F0F0F0u), r1 = (int)(w1 & 0xF0F0F0F0u);
+        const v4i p = v4i{r0, r1, (int)((w0 << 4) & 0xF0F0F0F0u), (int)((w1 << 4) & 0xF0F0F0F0u)};
+        if constexpr (plan.needQ[WC][X])
+          P[X][h] = __builtin_shufflevector(p, v4i{~r0, ~r1, 0, 0}, 0, 1, 2, 3, 4, 5);
+        else
+          P[X][h] = __builtin_shufflevector(p, p, 0, 1, 2, 3, -1, -1);
       }
     });
   };
-  auto mfma_h = [&](auto h, const v4i (&P)[NT][2]) {
+  auto mfma_h = [&](auto h, const v6i (&P)[NT][2]) {
     sfor<0, NU>([&](auto u) {
       constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u];
+      const v4i b = __builtin_shufflevector(P[J][h], P[J][h], 0, 1, 2, 3);
       if constexpr (plan.uIm[WC][u]) {
-        const v4i q = v4i{P[I][h][2], P[I][h][3], ~P[I][h][0], ~P[I][h][1]};
-        acc[u] = mfma32(q, P[J][h], acc[u]);
+        acc[u] = mfma32(__builtin_shufflevector(P[I][h], P[I][h], 2, 3, 4, 5), b, acc[u]);
       } else {
-        acc[u] = mfma32(P[I][h], P[J][h], acc[u]);
+        acc[u] = mfma32(__builtin_shufflevector(P[I][h], P[I][h], 0, 1, 2, 3), b, acc[u]);
       }
     });
   };
   // One block: reads of (st_rd, ks_rd), unpack of raw_up into P_up, MFMAs on
   // P_mm; with `loads` the loads of stage load_st go out mid-block.
   auto block = [&](auto loads, int st_rd, int ks_rd, v2i (&raw_rd)[NT][2], const v2i (&raw_up)[NT][2],
-                   v4i (&P_up)[NT][2], const v4i (&P_mm)[NT][2], int load_st) {
+                   v6i (&P_up)[NT][2], const v6i (&P_mm)[NT][2], int load_st) {
     read_step(st_rd, ks_rd, raw_rd);
     const uint8_t* g[C::LPW_MAX];
     if constexpr (loads.value) stage_src(load_st, g);
@@ -426,13 +412,14 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   // which block of a stage issues this wave's loads: alternate by wave so
   // that the workgroup's loads are spread over the stage
   constexpr int LOAD_BLOCK = DMA_STAGGER ? (WC & 1) : 0;
-  v4i P0[NT][2], P1[NT][2];
+  v6i P0[NT][2], P1[NT][2];
   v2i rawE[NT][2], rawO[NT][2];  // raw bytes of the even / odd K-step of a stage
   enter_stage(0);
   if (S - 1 < nstages) issue_stage(S - 1);
   read_step(0, 0, rawE);
   read_step(0, 1, rawO);
-  unpack(rawE, P0);
+  unpack_h(std::integral_constant<int, 0>{}, rawE, P0);
+  unpack_h(std::integral_constant<int, 1>{}, rawE, P0);
   using LoadsFirst = std::bool_constant<LOAD_BLOCK == 0>;
   using LoadsSecond = std::bool_constant<LOAD_BLOCK == 1>;
   int st = 0;
@@ -452,7 +439,8 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   unpack_h(std::integral_constant<int, 1>{}, rawO, P1);
   mfma_h(std::integral_constant<int, 1>{}, P0);
   interleave_half(std::false_type{});
-  mfma_step(P1);
+  mfma_h(std::integral_constant<int, 0>{}, P1);
+  mfma_h(std::integral_constant<int, 1>{}, P1);
   mfma_drain();
 
   // ---- epilogue: publish each column's Im' diagonal through LDS, then add
