@@ -50,7 +50,6 @@ namespace x32 {
 constexpr int STAGE_T = 64;           // time samples per ring stage
 constexpr int MAX_T_PER_WG = 32768;   // int32 headroom of the x256 sums
 constexpr int MAX_UNITS_PER_WAVE = 11;
-constexpr bool DMA_STAGGER = false;
 
 template <int B, int E, typename F>
 __device__ __forceinline__ void sfor(F&& f) {
@@ -409,9 +408,6 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
     mfma_h(std::integral_constant<int, 1>{}, P_mm);
     interleave_half(std::false_type{});
   };
-  // which block of a stage issues this wave's loads: alternate by wave so
-  // that the workgroup's loads are spread over the stage
-  constexpr int LOAD_BLOCK = DMA_STAGGER ? (WC & 1) : 0;
   v6i P0[NT][2], P1[NT][2];
   v2i rawE[NT][2], rawO[NT][2];  // raw bytes of the even / odd K-step of a stage
   enter_stage(0);
@@ -420,13 +416,11 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   read_step(0, 1, rawO);
   unpack_h(std::integral_constant<int, 0>{}, rawE, P0);
   unpack_h(std::integral_constant<int, 1>{}, rawE, P0);
-  using LoadsFirst = std::bool_constant<LOAD_BLOCK == 0>;
-  using LoadsSecond = std::bool_constant<LOAD_BLOCK == 1>;
   int st = 0;
   for (; st + S < nstages; ++st) {  // stage st + S is still to be loaded
     enter_stage(st + 1);
-    block(LoadsFirst{}, st + 1, 0, rawE, rawO, P1, P0, st + S);
-    block(LoadsSecond{}, st + 1, 1, rawO, rawE, P0, P1, st + S);
+    block(std::true_type{}, st + 1, 0, rawE, rawO, P1, P0, st + S);  // the loads go out here
+    block(std::false_type{}, st + 1, 1, rawO, rawE, P0, P1, st + S);
   }
   for (; st + 1 < nstages; ++st) {
     enter_stage(st + 1);
