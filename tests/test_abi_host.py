@@ -43,7 +43,8 @@ def test_host_helpers():
     assert X.xeng_strerror(12345) == "unknown status"
 
 
-@pytest.mark.parametrize("desc", [(0, 4, 10), (257, 4, 10), (8, 0, 10), (8, 4, 0), (8, 4, 16_777_216)])
+@pytest.mark.parametrize("desc", [(0, 4, 10), (257, 4, 10), (8, 0, 10), (8, 4, 0), (8, 4, 16_777_216),
+                                  (256, 8_388_608, 10)])   # F * N = 2^31: a time row past 32-bit offsets
 def test_plan_rejects_bad_shapes_before_touching_the_device(desc):
     from paper_1904_07778_amd import xeng as X
     with pytest.raises(X.XengError) as e:
