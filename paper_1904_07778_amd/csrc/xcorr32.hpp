@@ -183,23 +183,46 @@ __device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v
   const int mb = 4 * (lane >> 5);
   sfor<0, NU>([&](auto u) {
     constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u], IM = plan.uIm[WC][u];
-    const int j = 32 * J + n;
-    const int32_t bias = IM ? dcol[j] : 0;
-    sfor<0, 16>([&](auto v) {
-      const int i = 32 * I + 8 * (v / 4) + mb + (v % 4);
-      if ((N % 32 == 0 || i < N) && (J < I || j <= i)) {
-        int32_t* dst = accf + (i * (i + 1) / 2 + j) * 2 + IM;
-        int x;
-        asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(x) : "a"(acc[u][(int)v]));
-        x = (x - bias) >> 8;
-        if constexpr (MODE == EPI_ATOMIC)
-          atomicAdd(dst, x);
-        else if constexpr (MODE == EPI_ADD)
-          *dst += x;
-        else
-          *dst = x;
-      }
-    });
+    // the real and imaginary units of one tile pair, held by this wave one
+    // after the other: written together, one 8-byte (re, im) per baseline
+    constexpr bool PAIR = !IM && u + 1 < NU && plan.uI[WC][u + 1 < NU ? u + 1 : u] == I &&
+                          plan.uJ[WC][u + 1 < NU ? u + 1 : u] == J && plan.uIm[WC][u + 1 < NU ? u + 1 : u];
+    constexpr bool DONE = IM && u > 0 && plan.uI[WC][u > 0 ? u - 1 : 0] == I &&
+                          plan.uJ[WC][u > 0 ? u - 1 : 0] == J && !plan.uIm[WC][u > 0 ? u - 1 : 0];
+    if constexpr (!DONE) {
+      const int j = 32 * J + n;
+      const int32_t bias = (IM || PAIR) ? dcol[j] : 0;
+      sfor<0, 16>([&](auto v) {
+        const int i = 32 * I + 8 * (v / 4) + mb + (v % 4);
+        if ((N % 32 == 0 || i < N) && (J < I || j <= i)) {
+          int32_t* dst = accf + (i * (i + 1) / 2 + j) * 2;
+          int x;
+          asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(x) : "a"(acc[u][(int)v]));
+          if constexpr (PAIR) {
+            int y;
+            asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(y) : "a"(acc[u + 1][(int)v]));
+            const v2i re_im = v2i{x >> 8, (y - bias) >> 8};
+            v2i* d2 = reinterpret_cast<v2i*>(dst);
+            if constexpr (MODE == EPI_ATOMIC) {
+              atomicAdd(dst, re_im[0]);
+              atomicAdd(dst + 1, re_im[1]);
+            } else if constexpr (MODE == EPI_ADD) {
+              *d2 += re_im;
+            } else {
+              *d2 = re_im;
+            }
+          } else {
+            x = (x - bias) >> 8;
+            if constexpr (MODE == EPI_ATOMIC)
+              atomicAdd(dst + IM, x);
+            else if constexpr (MODE == EPI_ADD)
+              dst[IM] += x;
+            else
+              dst[IM] = x;
+          }
+        }
+      });
+    }
   });
 }
 
