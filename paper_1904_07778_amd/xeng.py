@@ -418,6 +418,8 @@ class Plan:
         ptrs, ts = self._marshal(voltages)
         if out is None:
             out = [None if v is None else self.new_output(a) for a, v in enumerate(voltages)]
+        if len(out) != len(self.specs):
+            raise ValueError("one output tensor (or None) per slot")
         for a, (o, s) in enumerate(zip(out, self.specs)):
             if o is None:
                 continue
