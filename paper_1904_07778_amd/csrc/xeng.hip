@@ -562,24 +562,31 @@ int xeng_correlate_dump(xeng_plan_t* p, const uint8_t* const* d_voltages, const 
   std::vector<Saved> redirected;
   xeng::DumpParams dp{};
   int64_t most = 0;
+  auto flush = [&]() -> int {
+    if (dp.count == 0) return XENG_OK;
+    const int64_t blocks = std::min<int64_t>((most + 1023) / 1024, 8LL * p->n_cu);
+    hipError_t e = xeng::dump_launch((int)std::max<int64_t>(1, blocks), p->stream, dp);
+    dp.count = 0;
+    most = 0;
+    return e == hipSuccess ? XENG_OK : hip_fail(p, e, "carry-over copy");
+  };
   for (int32_t a = 0; a < na; ++a) {
     ArrayState& s = p->arrays[a];
     if (!s.active || !d_dst[a] || n_time[a] == 0) continue;
     redirected.push_back(Saved{a, s.acc, s.clean, s.zeroed, s.n_integrated});
     if (!s.clean) {
-      if (dp.count == xeng::DUMP_MAX) return fail(p, XENG_EINVAL, "more than %d arrays to carry over", xeng::DUMP_MAX);
       dp.acc[dp.count] = reinterpret_cast<const int2*>(s.acc);
       dp.dst[dp.count] = reinterpret_cast<int2*>(d_dst[a]);
       dp.n[dp.count] = (int64_t)(s.acc_bytes / sizeof(int2));
       most = std::max(most, dp.n[dp.count]);
-      ++dp.count;
+      if (++dp.count == xeng::DUMP_MAX) {
+        st = flush();
+        if (st != XENG_OK) return st;
+      }
     }
   }
-  if (dp.count > 0) {
-    const int64_t blocks = std::min<int64_t>((most + 1023) / 1024, 8LL * p->n_cu);
-    hipError_t e = xeng::dump_launch((int)std::max<int64_t>(1, blocks), p->stream, dp);
-    if (e != hipSuccess) return hip_fail(p, e, "carry-over copy");
-  }
+  st = flush();
+  if (st != XENG_OK) return st;
   for (const Saved& r : redirected) {
     ArrayState& s = p->arrays[r.a];
     s.acc = d_dst[r.a];
