@@ -65,8 +65,16 @@ __global__ __launch_bounds__(CTHREADS) void channelise(const int8_t* __restrict_
   extern __shared__ float2 lds[];  // [2][G][L]
   float2* buf0 = lds;
   float2* buf1 = lds + G * L;
-  const int q0 = blockIdx.x * G;   // first pair
-  const int64_t s = blockIdx.y;
+  // Work item w = (spectrum, pair group), pair group fastest.  Workgroups are
+  // dealt to the 8 XCDs in turn; each XCD takes a contiguous range of w, so
+  // the pairs of one spectrum, whose outputs interleave in the same 128-byte
+  // lines of [spectrum][channel][input], are written through one L2.
+  const int64_t total = (int64_t)gridDim.x * gridDim.y;
+  const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const int64_t xq = total / 8, xr = total % 8, xcd = b % 8;
+  const int64_t w = xcd * xq + (xcd < xr ? xcd : xr) + b / 8;
+  const int q0 = (int)(w % gridDim.x) * G;   // first pair
+  const int64_t s = w / gridDim.x;
   const int F = L / 2;
   const float* h = tab;
   const float2* tw = reinterpret_cast<const float2*>(tab + TAPS * L);
