@@ -28,6 +28,15 @@ HIPCC_FLAGS = [
     # the enclosing loop is unrolled; every loop ends up fully unrolled
     "-Wno-pass-failed",
 ]
+# Units of the 16-row-tile kernel: the register allocator's default order
+# keeps some of the many 4-register accumulator tuples in different registers
+# at the top and the bottom of the main loop and moves them around with
+# accvgpr copies every iteration; assigning local ranges in reverse order
+# keeps every accumulator in place (checked in the generated assembly).
+PER_FILE_FLAGS = {
+    "k_x16_": ["-mllvm", "-greedy-reverse-local-assignment"],
+    "k_batch": ["-mllvm", "-greedy-reverse-local-assignment"],
+}
 # the host pass warns that it does not know the packed-fp32 feature
 _NOISE = ("'-packed-fp32-ops' is not a recognized feature",)
 
@@ -46,12 +55,24 @@ def build(verbose: bool = False, incremental: bool = False, jobs: int | None = N
     headers = glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
     newest_header = max(os.path.getmtime(h) for h in headers)
 
+    def deps_of(obj):
+        """Headers the object was built from (its -MMD file), or None."""
+        try:
+            with open(obj + ".d") as fh:
+                text = fh.read().replace("\\\n", " ")
+        except OSError:
+            return None
+        return [t for t in text.split(":", 1)[1].split() if t.endswith((".h", ".hpp"))]
+
     def compile_one(src):
         obj = os.path.join(OBJ, os.path.basename(src).replace(".hip", ".o"))
-        if incremental and os.path.exists(obj) and \
-                os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header):
-            return obj
-        cmd = ["hipcc", *HIPCC_FLAGS, "-c", src, "-o", obj]
+        if incremental and os.path.exists(obj):
+            deps = deps_of(obj)
+            newest = newest_header if deps is None else max([os.path.getmtime(d) for d in deps if os.path.exists(d)] or [0])
+            if os.path.getmtime(obj) > max(os.path.getmtime(src), newest):
+                return obj
+        extra = [f for key, flags in PER_FILE_FLAGS.items() if os.path.basename(src).startswith(key) for f in flags]
+        cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-MMD", "-MF", obj + ".d", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         _run(cmd)

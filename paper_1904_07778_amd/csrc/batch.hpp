@@ -6,8 +6,9 @@
 // work is cut into items (array, channel group, time chunk) and a single
 // persistent grid of one workgroup per compute unit pulls items from work
 // queues until all are done.  Every item runs the same per-wave body as the
-// plain launch (x32::wave_main) with the launch shape compiled for its N, so
-// the sums are bit-identical to the plain engine's.
+// plain launch of the 16-row-tile kernel (x16::wave_main) with the launch
+// shape compiled for its N, so the sums are bit-identical to the plain
+// engine's.
 //
 // Queues.  There is one queue per XCD (workgroup w runs on XCD w % 8).  Each
 // array's channel groups are cut into 8 contiguous ranges, one per queue;
@@ -23,7 +24,7 @@
 // launch (for instance the next replay of a captured graph) finds them zero
 // without any memset.
 #pragma once
-#include "xcorr32.hpp"
+#include "xcorr16.hpp"
 
 namespace xeng {
 namespace batch {
@@ -53,7 +54,8 @@ constexpr int lds_bytes() {
   if constexpr (N > MAX_N) {
     return 0;
   } else {
-    constexpr int own = x32::Shape<N, x32::cpw_for(N), x32::stages_for(N)>::LDS_BYTES;
+    constexpr int own =
+        x16::Shape<N, x16::cpw_for(N), x16::stages_for(N, x16::KPS_DEFAULT), x16::KPS_DEFAULT>::LDS_BYTES;
     constexpr int rest = lds_bytes<N + 16>();
     return own > rest ? own : rest;
   }
@@ -63,7 +65,7 @@ template <int N>
 __device__ __forceinline__ void run_if(int n, const Args& a, uint8_t* lds, int group, int tchunk, int tid) {
   if constexpr (N <= MAX_N) {
     if (n == N)
-      x32::run_item<N>(a, lds, group, tchunk, tid);
+      x16::run_item<N, x16::KPS_DEFAULT>(a, lds, group, tchunk, tid);
     else
       run_if<N + 16>(n, a, lds, group, tchunk, tid);
   }

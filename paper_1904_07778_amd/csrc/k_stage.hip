@@ -25,7 +25,7 @@ template <int NT>
 constexpr KernelInfo stage_info() {
   using SH = StageShape<NT>;
   using C = Cfg<NT, SH::W, SH::CPW>;
-  return KernelInfo{NT, SH::W, SH::CPW, 2, C::THREADS, C::LDS_BYTES, XENG_MAX_T_PER_WG_STAGE,
+  return KernelInfo{NT, SH::W, SH::CPW, 2, C::THREADS, C::LDS_BYTES, XENG_MAX_T_PER_WG_STAGE, 0, 16,
                     &launch_stage<NT>};
 }
 

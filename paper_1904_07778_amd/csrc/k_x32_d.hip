@@ -18,7 +18,7 @@ template <int N>
 constexpr KernelInfo info() {
   constexpr int CPW = cpw_for(N), S = stages_for(N);
   using C = Shape<N, CPW, S>;
-  return KernelInfo{C::NT, C::W, CPW, S, C::THREADS, C::LDS_BYTES, MAX_T_PER_WG, &launch<N>};
+  return KernelInfo{C::NT, C::W, CPW, S, C::THREADS, C::LDS_BYTES, MAX_T_PER_WG, 0, 32, &launch<N>};
 }
 
 constexpr int kN[4] = {208, 224, 240, 256};

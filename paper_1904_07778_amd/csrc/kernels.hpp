@@ -12,6 +12,8 @@ using LaunchFn = hipError_t (*)(dim3 grid, hipStream_t s, const Args& a);
 struct KernelInfo {
   int nt, w, cpw, stages, threads, lds_bytes;
   int64_t max_t_per_wg;  // longest time range one workgroup may integrate
+  int64_t max_row_bytes; // largest time row F*N the kernel addresses (0: any)
+  int tile_rows;         // rows of its tiles: 16 or 32
   LaunchFn launch;
 };
 
@@ -28,6 +30,21 @@ inline const KernelInfo* x32_kernel(int n) {
   if (!k) k = x32_kernel_b(n);
   if (!k) k = x32_kernel_c(n);
   if (!k) k = x32_kernel_d(n);
+  return k;
+}
+// 16-row-tile ring kernel on v_mfma_i32_16x16x64_i8, N a multiple of 16 up
+// to 240 (several translation units; x16_kernel asks each).
+const KernelInfo* x16_kernel_a(int n);
+const KernelInfo* x16_kernel_b(int n);
+const KernelInfo* x16_kernel_c(int n);
+const KernelInfo* x16_kernel_d(int n);
+const KernelInfo* x16_kernel_e(int n);
+inline const KernelInfo* x16_kernel(int n) {
+  const KernelInfo* k = x16_kernel_a(n);
+  if (!k) k = x16_kernel_b(n);
+  if (!k) k = x16_kernel_c(n);
+  if (!k) k = x16_kernel_d(n);
+  if (!k) k = x16_kernel_e(n);
   return k;
 }
 

@@ -111,16 +111,29 @@ bool valid_desc(const xeng_array_desc& d) {
          d.max_time_per_call >= 1 && d.max_time_per_call <= XENG_MAX_INTEGRATION;
 }
 
-// Default kernel for N: 32-row ring kernel when N is a multiple of 16, else
-// the staging kernel of 16-row tiles.
-const KernelInfo* default_kernel(int32_t n) {
-  return (n % 16 == 0) ? xeng::x32_kernel(n) : xeng::stage_kernel((n + 15) / 16);
+bool kernel_fits(const KernelInfo* k, const xeng_array_desc& d) {
+  return k && (k->max_row_bytes == 0 || (int64_t)d.n_chans * d.n_inputs <= k->max_row_bytes);
+}
+
+// Default kernel for an array: the 16-row-tile ring kernel when N is a
+// multiple of 16 it is built for (and its time rows fit its 32-bit offsets),
+// else the 32-row-tile ring kernel when N is a multiple of 16, else the
+// staging kernel of 16-row tiles.
+const KernelInfo* default_kernel(const xeng_array_desc& d) {
+  const int32_t n = d.n_inputs;
+  if (n % 16 == 0) {
+    const KernelInfo* k = xeng::x16_kernel(n);
+    if (kernel_fits(k, d)) return k;
+    k = xeng::x32_kernel(n);
+    if (k) return k;
+  }
+  return xeng::stage_kernel((n + 15) / 16);
 }
 
 int init_slot(xeng_plan_t* p, ArrayState& s, const xeng_array_desc& d) {
   s = ArrayState{};
   s.d = d;
-  s.k = default_kernel(d.n_inputs);
+  s.k = default_kernel(d);
   s.acc_bytes = (size_t)d.n_chans * nbl_of(d.n_inputs) * 2 * sizeof(int32_t);
   hipError_t e = hipMalloc(&s.acc, s.acc_bytes);
   if (e != hipSuccess) {
@@ -198,8 +211,12 @@ constexpr double ITEM_START_CYCLES = 4000.0;  // ring fill and epilogue of one i
 constexpr double HBM_BYTES_PER_CYCLE = 13.0;  // 8 TB/s over 256 CUs at 2.4 GHz
 
 double cycles_per_sample(const KernelInfo* k, int32_t n) {
-  const int nt = (n + 31) / 32;
-  const double mfma = (double)nt * (nt + 1) * k->cpw / 2.0;  // 32 cycles per 32 samples per unit, 4 SIMDs
+  // units (real or imaginary product of one tile pair) per channel; a 32-row
+  // unit takes 32 MFMA cycles per 16 samples, a 16-row unit 16 cycles per 32
+  // samples; a workgroup's four SIMDs share its CPW channels' units
+  const int nt = (n + k->tile_rows - 1) / k->tile_rows;
+  const double per_unit = k->tile_rows == 32 ? 2.0 : 0.5;
+  const double mfma = (double)nt * (nt + 1) * per_unit * k->cpw / 4.0;
   const double hbm = (double)k->cpw * n / HBM_BYTES_PER_CYCLE;
   return mfma > hbm ? mfma : hbm;
 }
@@ -218,7 +235,7 @@ int record_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_tim
   for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) {
     const ArrayState& s = p->arrays[a];
     if (!s.active || n_time[a] == 0) continue;
-    if (!xeng::batch::supports(s.d.n_inputs) || s.k != xeng::x32_kernel(s.d.n_inputs)) {
+    if (!xeng::batch::supports(s.d.n_inputs) || s.k != xeng::x16_kernel(s.d.n_inputs)) {
       others.push_back(a);
       continue;
     }
@@ -665,7 +682,10 @@ int xeng_autotune(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_
     for (ArrayState& s : p->arrays) {
       if (!s.active) continue;
       std::vector<const KernelInfo*> kernels;
-      if (s.d.n_inputs % 16 == 0) kernels.push_back(xeng::x32_kernel(s.d.n_inputs));
+      if (s.d.n_inputs % 16 == 0) {
+        if (kernel_fits(xeng::x16_kernel(s.d.n_inputs), s.d)) kernels.push_back(xeng::x16_kernel(s.d.n_inputs));
+        kernels.push_back(xeng::x32_kernel(s.d.n_inputs));
+      }
       kernels.push_back(xeng::stage_kernel((s.d.n_inputs + 15) / 16));
       const KernelInfo* pick_k = s.k;
       int pick_split = s.split;
