@@ -64,7 +64,7 @@ PEAK_INT8_TOPS = 5000.0      # MI355X dense int8 MFMA, 5.0 POP/s
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 OPS_PER_CMAC = 8             # 4 int8 multiplies + 4 adds per complex MAC
 REALTIME_SPECTRA_PER_S = 125e6   # 250 MSPS real sampling -> 125e6 complex samples/s/input
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "xcorr_cylinder_counters.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_1904_07778_amd", "csrc")
 
 
@@ -72,9 +72,9 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-# sources of the timed kernel (the N=192 ring kernel); its counters go stale
-# when any of them changes
-KERNEL_SOURCES = ("xcorr.hpp", "xcorr32.hpp", "k_x32_c.hip")
+# sources of the timed kernels (the 16-row-tile ring kernel and its
+# instantiations); their counters go stale when any of them changes
+KERNEL_SOURCES = ("xcorr.hpp", "xcorr16.hpp", "k_x16_a.hip", "k_x16_c.hip")
 
 
 def kernel_source_hash() -> str:
@@ -86,39 +86,44 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source."""
+def measured_traffic(workload: str, calls: int = 1):
+    """HBM bytes per step from the committed rocprofv3 counter summary of this
+    workload (profiles/xcorr_<workload>_counters.txt), or None when it is
+    missing, was taken on another workload or on different kernel sources."""
+    path = os.path.join(PROFILES, f"xcorr_{workload}_counters.txt")
     try:
-        with open(COUNTERS_FILE) as fh:
+        with open(path) as fh:
             rec = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
     except OSError:
         return None
     rec = {k.strip(): v.strip() for k, v in rec.items()}
-    if rec.get("kernel_source_sha1") != kernel_source_hash():
+    if rec.get("workload") != workload or rec.get("kernel_source_sha1") != kernel_source_hash():
         return None
     try:
-        return float(rec["hbm_bytes_per_launch"])
+        return float(rec["hbm_bytes_per_step"])
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(v, seconds: float):
-    """The oracle as it stands, on whole channels of the same input, until
-    about `seconds` of wall time have been spent."""
+def cpu_baseline(blocks, seconds: float):
+    """The oracle as it stands, on whole channels of the same input (every
+    block of the integration), until about `seconds` of wall time have been
+    spent."""
     import oracle
-    T, F, N = v.shape
+    T, F, N = blocks[0].shape
     nbl = N * (N + 1) // 2
     chunk = 16
     done, t0 = 0, time.perf_counter()
     while done < F and time.perf_counter() - t0 < seconds:
         f1 = min(F, done + chunk)
-        oracle.accumulate(v, chans=(done, f1))
+        acc = None
+        for b in blocks:
+            acc = oracle.accumulate(b, acc, chans=(done, f1))
         done = f1
     dt = time.perf_counter() - t0
-    return {"value": nbl * done * T / dt, "unit": "CMAC/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"{done} of {F} channels (N={N}, T={T}) of the same input, {dt:.1f} s"}
+    return {"value": nbl * done * T * len(blocks) / dt, "unit": "CMAC/s", "cores": oracle.max_threads(),
+            "kind": "oracle", "host_cpu": host_cpu_model(), "build": oracle.BUILD_FLAGS,
+            "sample": f"{done} of {F} channels (N={N}, {len(blocks)} x T={T}) of the same input, {dt:.1f} s"}
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5) -> None:
@@ -140,9 +145,11 @@ def main() -> int:
     ap.add_argument("--workload", default="cylinder",
                     choices=["cylinder", "dish", "dish_tiny", "batch", "stream", "requant", "ingest", "chan"])
     ap.add_argument("--stream-dumps", type=int, default=4, help="dumps per request (stream, saturating)")
-    ap.add_argument("--paced-seconds", type=float, default=6.0, help="length of the paced run (stream)")
+    ap.add_argument("--paced-seconds", type=float, default=30.0, help="length of each paced run (stream)")
     ap.add_argument("--stream-ring", type=int, default=16, help="device ring depth in blocks per sub-array (stream)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--settle-seconds", type=float, default=1.0,
+                    help="untimed run of the step before the warm-up (plain workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -178,59 +185,119 @@ def main() -> int:
     if args.workload == "chan":
         return bench_chan(args)
 
-    w = synth.WORKLOADS[args.workload]
-    N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
+    return bench_plain(args)
+
+
+def host_cpu_model() -> str:
+    """Model name of the host CPU (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def bench_plain(args) -> int:
+    """Plain engine on one workload: cylinder (default), dish or dish_tiny.
+
+    One step = one integration: `calls` xeng_correlate calls of T samples
+    (the last one fused with the dump into a device buffer:
+    xeng_correlate_dump).  The plan is autotuned first, then the step runs
+    for --settle-seconds (untimed, so the shader clock reaches its level
+    under this load), then W warm-up and K timed steps.  Every engine call of
+    the timed steps is bracketed by HIP events on the engine's stream."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1904_07778_amd.xeng import Plan
+
+    name = args.workload
+    w = synth.WORKLOADS[name]
+    N, F, T, calls = w["n_inputs"], w["n_chans"], w["n_time"], w["calls"]
     nbl = N * (N + 1) // 2
-    log(f"generating {args.workload}: N={N} F={F} T={T} ({T * F * N / 1e9:.2f} GB)")
+    log(f"generating {name}: N={N} F={F} T={T} x {calls} calls ({calls * T * F * N / 1e9:.2f} GB)")
     t0 = time.perf_counter()
-    v_host = synth.voltages(w["recipe"], w["seed"], N, F, T)
+    v_host = [synth.voltages(w["recipe"], w["seed"], N, F, T, block=b) if calls > 1 else
+              synth.voltages(w["recipe"], w["seed"], N, F, T) for b in range(calls)]
     log(f"generated in {time.perf_counter() - t0:.1f} s")
-    v = torch.from_numpy(v_host).cuda()
+    v = [torch.from_numpy(h).cuda() for h in v_host]
 
     stream = torch.cuda.Stream()
     plan = Plan([(N, F, T)], stream=stream)
     out = plan.new_output(0)
     torch.cuda.synchronize()
+    tuned_ms = plan.autotune([v[0]], reps=3)
+    log(f"autotuned: {tuned_ms:.4f} ms per call")
 
-    # A step is one integration of T samples delivered into `out`: the fused
-    # call (the kernel writes the visibilities straight into `out`).  The
-    # separate correlate + dump calls (accumulator, then a copy) are timed
-    # after it for comparison.
+    def step(events=None):
+        for k in range(calls):
+            if events is not None:
+                events[k][0].record(stream)
+            if k + 1 < calls:
+                plan.correlate([v[k]])
+            else:
+                plan.correlate_dump([v[k]], out=[out])
+            if events is not None:
+                events[k][1].record(stream)
+
+    t_settle = time.perf_counter()
+    n_settle = 0
+    while time.perf_counter() - t_settle < args.settle_seconds:
+        step()
+        n_settle += 1
+        if n_settle % 8 == 0:
+            torch.cuda.synchronize()
     for _ in range(args.warmup):
-        plan.correlate_dump([v], out=[out])
-        plan.correlate([v])
-        plan.dump(0, out=[out])
+        step()
     torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
+    log(f"settled ({n_settle} steps in {time.perf_counter() - t_settle:.1f} s), warmup {args.warmup} done")
 
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(calls)]
+          for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
-        ev0[k].record(stream)
-        plan.correlate_dump([v], out=[out])
-        ev1[k].record(stream)
+        step(ev[k])
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     log(f"timed {args.steps} steps in {t_total:.3f} s")
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
+    call_ms = np.array([[a.elapsed_time(b) for a, b in e] for e in ev])   # [steps][calls]
+    step_dev_ms = call_ms.sum(axis=1)
 
-    torch.cuda.synchronize()
-    t_sep = time.perf_counter()
-    for k in range(args.steps):
-        plan.correlate([v])
-        plan.dump(0, out=[out])
-    torch.cuda.synchronize()
-    ms_separate = 1e3 * (time.perf_counter() - t_sep) / args.steps
-    log(f"separate correlate + dump: {ms_separate:.4f} ms per step")
+    ms_separate = None
+    if calls == 1:
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter()
+        for k in range(args.steps):
+            plan.correlate([v[0]])
+            plan.dump(0, out=[out])
+        torch.cuda.synchronize()
+        ms_separate = 1e3 * (time.perf_counter() - t_sep) / args.steps
+        log(f"separate correlate + dump: {ms_separate:.4f} ms per step")
 
     ms_per_step = 1e3 * t_total / args.steps
-    cmac_per_step = nbl * F * T
+    cmac_per_step = nbl * F * T * calls
     value = cmac_per_step / (ms_per_step / 1e3)
-    achieved_tops = cmac_per_step * OPS_PER_CMAC / (kernel_ms / 1e3) / 1e12
-    in_bytes, out_bytes = T * F * N, F * nbl * 8
-    traffic = measured_traffic()
+    in_bytes, out_bytes = calls * T * F * N, F * nbl * 8
+    alg_bytes = in_bytes + out_bytes
+    dev_mean = float(step_dev_ms.mean())
+    hbm_bound = 4 * (N + 1) < PEAK_INT8_TOPS / PEAK_HBM_GBS * 1e3
+    if hbm_bound:
+        achieved = alg_bytes / (dev_mean / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    else:
+        achieved = cmac_per_step * OPS_PER_CMAC / (dev_mean / 1e3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+                "frac": achieved / PEAK_INT8_TOPS}
+    roof.update({"traffic": measured_traffic(name, calls), "algorithmic_bytes": alg_bytes,
+                 "hbm_gbs_algorithmic": alg_bytes / (dev_mean / 1e3) / 1e9,
+                 "int8_tops": cmac_per_step * OPS_PER_CMAC / (dev_mean / 1e3) / 1e12,
+                 "time": "mean of the per-step sums of the engine calls' HIP-event durations"})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -238,8 +305,8 @@ def main() -> int:
         cpu = cpu_baseline(v_host, args.cpu_seconds)
 
     rec = {
-        "metric": "X-engine complex MAC/s at N=192 (Hermitian triangle incl. autos), "
-                  "int8-MFMA fraction and real-time factor",
+        "metric": "X-engine complex MAC/s (Hermitian triangle incl. autos), int8-MFMA fraction at "
+                  "N=192 and real-time factor",
         "value": value,
         "unit": "CMAC/s",
         "n_gpus": 1,
@@ -251,22 +318,26 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "int8",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: N={N} inputs, F={F} channels, "
-                               f"T={T} samples per integration, 4+4-bit complex",
-                   "n_inputs": N, "n_chans": F, "n_time": T,
-                   "step": "correlate + dump in one call (xeng_correlate_dump)"},
-        "ms_per_step_separate_calls": ms_separate,
+        "config": {"workload": f"{name}: N={N} inputs, F={F} channels, {calls} x T={T} samples per "
+                               "integration, 4+4-bit complex",
+                   "n_inputs": N, "n_chans": F, "n_time": T, "calls_per_integration": calls,
+                   "step": ("correlate + dump in one call (xeng_correlate_dump)" if calls == 1 else
+                            f"{calls - 1} xeng_correlate calls, then xeng_correlate_dump"),
+                   "settle_s": args.settle_seconds, "autotuned_ms_per_call": tuned_ms},
+        "kernel_ms": dev_mean,
+        "kernel_ms_median": float(np.median(step_dev_ms)),
+        "kernel_ms_min": float(step_dev_ms.min()),
+        "kernel_ms_max": float(step_dev_ms.max()),
         "int8_mfma_frac_of_step": value * OPS_PER_CMAC / (PEAK_INT8_TOPS * 1e12),
+        "int8_mfma_frac_kernel_median": cmac_per_step * OPS_PER_CMAC / (float(np.median(step_dev_ms)) / 1e3)
+                                        / (PEAK_INT8_TOPS * 1e12),
         "rtf": value / (nbl * REALTIME_SPECTRA_PER_S),
         "rtf_full_matrix_reading": value / (nbl * REALTIME_SPECTRA_PER_S) / 2,
-        "kernel_ms": kernel_ms,
-        "roofline": {"bound": "mfma" if 4 * (N + 1) >= PEAK_INT8_TOPS / PEAK_HBM_GBS * 1e3 else "hbm",
-                     "achieved": achieved_tops, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                     "frac": achieved_tops / PEAK_INT8_TOPS, "traffic": traffic,
-                     "algorithmic_bytes": in_bytes + out_bytes,
-                     "hbm_gbs_algorithmic": (in_bytes + out_bytes) / (kernel_ms / 1e3) / 1e9},
+        "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if ms_separate is not None:
+        rec["ms_per_step_separate_calls"] = ms_separate
     print(json.dumps(rec), flush=True)
     plan.close()
     return 0
@@ -358,23 +429,27 @@ def bench_batch(args) -> int:
 
 
 def bench_stream(args) -> int:
-    """Streaming workload: serving loop vs plain per-block launches."""
+    """Streaming workload: the serving loop, with blocks pre-staged in device
+    rings and with blocks copied in from pinned host rings (H2D-inclusive),
+    saturating and paced, against plain per-block launches."""
     import numpy as np
     import torch
 
     import synth
-    from paper_1904_07778_amd.serve import (BLOCK_T, Feed, Request, Server, drive, latency_stats,
+    from paper_1904_07778_amd.serve import (BLOCK_T, Feed, HostFeed, Request, Server, drive, latency_stats,
                                             realtime_period)
     from paper_1904_07778_amd.xeng import Plan
 
     subs = synth.stream_subarrays()
     ring_blocks = args.stream_ring
     log(f"stream workload: {subs}")
-    rings = {}
+    hosts, rings = {}, {}
     for k, s in enumerate(subs):
         n, f = s["n_inputs"], s["n_chans"]
-        rings[(n, f)] = torch.from_numpy(synth.voltages("sources", 5, n, f, ring_blocks * BLOCK_T,
-                                                        array=k, n_src=1)).cuda()
+        h = synth.voltages("sources", 5, n, f, ring_blocks * BLOCK_T, array=k, n_src=1)
+        hosts[(n, f)] = torch.from_numpy(h).pin_memory()
+        rings[(n, f)] = hosts[(n, f)].cuda()
+    copy_stream = torch.cuda.Stream()
 
     def requests(n_dumps_of, waves=2):
         reqs = []
@@ -384,23 +459,37 @@ def bench_stream(args) -> int:
                                     s["dump_len"], n_dumps_of(s), ring_blocks=ring_blocks))
         return reqs
 
-    def feeds_for(reqs):
-        return {r.name: Feed(rings[(r.n_inputs, r.n_chans)], r.n_dumps * r.dump_len // BLOCK_T)
-                for r in reqs}
+    def feeds_for(reqs, h2d):
+        out = {}
+        for r in reqs:
+            key, nb = (r.n_inputs, r.n_chans), r.n_dumps * r.dump_len // BLOCK_T
+            if h2d:   # each request copies into a device ring of its own
+                out[r.name] = HostFeed(hosts[key], torch.empty_like(rings[key]), nb, copy_stream)
+            else:     # pre-staged: requests of one shape read the same device ring
+                out[r.name] = Feed(rings[key], nb)
+        return out
 
     fps = [r.footprint() for r in requests(lambda s: 1, waves=1)]
     budget = sum(fps)            # one wave fits; the second waits for memory
     real_need = sum(s["n_inputs"] * (s["n_inputs"] + 1) // 2 * REALTIME_SPECTRA_PER_S for s in subs)
-
-    # saturating: the serving loop
     reqs = requests(lambda s: args.stream_dumps)
     cmac = sum(r.n_inputs * (r.n_inputs + 1) // 2 * r.n_chans * r.n_dumps * r.dump_len for r in reqs)
-    drive(Server(budget, keep_results=False), [(0.0, r) for r in requests(lambda s: 1)],
-          feeds_for(requests(lambda s: 1)), paced=False)        # warm-up (graphs, allocator)
-    srv = Server(budget, keep_results=False)
-    t_serve = drive(srv, [(0.0, r) for r in reqs], feeds_for(reqs), paced=False)
-    srv.close()
-    log(f"serving loop: {t_serve:.3f} s for {cmac:.3e} CMAC, {srv.iterations} engine calls")
+    in_bytes = sum(r.n_inputs * r.n_chans * r.n_dumps * r.dump_len for r in reqs)
+
+    def saturating(h2d):
+        warm = requests(lambda s: 1)
+        drive(Server(budget, keep_results=False), [(0.0, r) for r in warm], feeds_for(warm, h2d),
+              paced=False)                                   # warm-up (graphs, allocator)
+        rq = requests(lambda s: args.stream_dumps)
+        srv = Server(budget, keep_results=False)
+        t = drive(srv, [(0.0, r) for r in rq], feeds_for(rq, h2d), paced=False, time_limit=600)
+        srv.close()
+        log(f"serving loop ({'h2d' if h2d else 'pre-staged'}): {t:.3f} s for {cmac:.3e} CMAC, "
+            f"{srv.iterations} engine calls, {latency_stats(srv.done)}")
+        return t, srv
+
+    t_serve, srv = saturating(False)
+    t_serve_h2d, srv_h2d = saturating(True)
 
     # saturating: plain loop, one launch per block per sub-array, round robin
     stream = torch.cuda.Stream()
@@ -434,14 +523,20 @@ def bench_stream(args) -> int:
     # paced: blocks at the real-time rate, latency of every dump
     def paced_dumps(s):
         return max(1, int(round(args.paced_seconds / (s["dump_len"] / BLOCK_T * realtime_period(s["n_chans"])))))
-    preqs = requests(paced_dumps, waves=1)
-    psrv = Server(budget, keep_results=False)
-    t_paced = drive(psrv, [(0.0, r) for r in preqs], feeds_for(preqs), paced=True,
-                    time_limit=4 * args.paced_seconds + 60)
-    psrv.close()
-    lat = latency_stats(psrv.done)
-    per = {r.name: latency_stats([d for d in psrv.done if d.name == r.name]) for r in preqs}
-    log(f"paced: {t_paced:.2f} s, {lat}")
+
+    def paced(h2d):
+        preqs = requests(paced_dumps, waves=1)
+        psrv = Server(budget, keep_results=False)
+        t = drive(psrv, [(0.0, r) for r in preqs], feeds_for(preqs, h2d), paced=True,
+                  time_limit=4 * args.paced_seconds + 60)
+        psrv.close()
+        lat = latency_stats(psrv.done)
+        per = {r.name: latency_stats([d for d in psrv.done if d.name == r.name]) for r in preqs}
+        log(f"paced ({'h2d' if h2d else 'pre-staged'}): {t:.2f} s, {lat}")
+        return {"seconds": t, **lat, "per_subarray": per}
+
+    paced_pre = paced(False)
+    paced_h2d = paced(True)
 
     value = cmac / t_serve
     rec = _base_record(args, "X-engine complex MAC/s of the streaming serving loop (saturating)",
@@ -456,7 +551,15 @@ def bench_stream(args) -> int:
     rec.update({
         "plain_value": cmac / t_plain, "speedup_vs_plain": t_plain / t_serve,
         "rtf": value / real_need,
-        "paced": {"seconds": t_paced, **lat, "per_subarray": per},
+        "saturating_latency": latency_stats(srv.done),
+        "h2d": {"value": cmac / t_serve_h2d, "unit": "CMAC/s", "rtf": cmac / t_serve_h2d / real_need,
+                "seconds": t_serve_h2d, "engine_calls": srv_h2d.iterations,
+                "h2d_gbs": in_bytes / t_serve_h2d / 1e9,
+                "saturating_latency": latency_stats(srv_h2d.done),
+                "note": "blocks copied from pinned host rings into per-request device rings on a copy "
+                        "stream, ordered by events against the engine calls"},
+        "paced": paced_pre,
+        "paced_h2d": paced_h2d,
         "roofline": None, "cpu_baseline": None,
     })
     print(json.dumps(rec), flush=True)

@@ -14,9 +14,11 @@ Here the same chain serves several independent sub-arrays at once on one GPU:
   leaves when its last dump is out; requests that arrive meanwhile wait in
   order and are admitted as memory frees up (xeng_attach / xeng_detach on
   one batched plan).
-* Voltage blocks (uint8 [1024][F][N], already in HBM, or copied in from
-  pinned host memory on a copy stream) arrive continuously, each with a
-  sequence number.  A gap in the numbers is counted as lost samples; the
+* Voltage blocks (uint8 [1024][F][N]) arrive continuously, each with a
+  sequence number: either pre-staged in a device ring (Feed), or in a pinned
+  host ring from which a copy stream moves each block into a device ring,
+  ordered by events against the engine calls that read it (HostFeed, the
+  H2D-inclusive form).  A gap in the numbers is counted as lost samples; the
   integration simply has fewer samples, reported with the dump.
 * Each iteration makes ONE xeng_correlate call over every resident slot: the
   blocks a slot has ready (consecutive in its ring, up to its next dump
@@ -73,6 +75,8 @@ class Block:
     ring: object = None    # the ring tensor data is a slice of (for coalescing)
     row: int = 0           # first time row of data in ring
     arrival: float = 0.0   # host time the block became available
+    ready: object = None   # event after which data is valid (its host-to-device copy), or None
+    on_consumed: object = None  # called with an event recorded after the engine call that read it
 
 
 @dataclass
@@ -230,7 +234,7 @@ class Server:
         s.covered += n * BLOCK_T
         s.integrated += n * BLOCK_T
         s.last_arrival = max(b.arrival for b in blocks)
-        return data
+        return data, blocks
 
     def step(self) -> bool:
         """Admit what fits, correlate every slot's ready blocks in one call,
@@ -242,13 +246,19 @@ class Server:
         n_slots = len(self.plan.specs)
         volts = [None] * n_slots
         issued = False
+        taken = []
         for s in self.slots.values():
-            d = self._take(s)
-            if d is not None:
+            got = self._take(s)
+            if got is not None:
+                d, blocks = got
                 volts[s.slot] = d
+                taken.extend(blocks)
                 nbl = s.req.n_inputs * (s.req.n_inputs + 1) // 2
                 self.cmac += nbl * s.req.n_chans * d.shape[0]
                 issued = True
+        for b in taken:                 # blocks still being copied in from host memory
+            if b.ready is not None:
+                self.plan.stream.wait_event(b.ready)
         fused = {}
         if issued:
             # slots whose integration this block completes are integrated and
@@ -267,6 +277,12 @@ class Server:
             else:
                 self.plan.correlate(volts)
             self.iterations += 1
+            if any(b.on_consumed is not None for b in taken):
+                ev = self.torch.cuda.Event()
+                ev.record(self.plan.stream)
+                for b in taken:
+                    if b.on_consumed is not None:
+                        b.on_consumed(ev)
         for name in list(self.slots):
             s = self.slots[name]
             if s.covered >= s.req.dump_len:
@@ -374,6 +390,39 @@ class Feed:
     def block(self, seq: int, arrival: float) -> Block:
         row = (seq % self.ring_blocks) * BLOCK_T
         return Block(seq, self.ring[row: row + BLOCK_T], self.ring, row, arrival)
+
+
+class HostFeed(Feed):
+    """Block source in host memory, the H2D-inclusive form of the network
+    thread's ring (Sec. 2.2): blocks arrive in a pinned host ring and are
+    copied into a device ring on a copy stream.
+
+    Block seq comes from host rows (seq % R_host) * BLOCK_T .. and lands in
+    device ring slot seq % R_dev.  Its copy waits for the engine call that
+    read the slot's previous block (event from the server), and the engine
+    waits for the copy (the block's ready event) before it reads the block."""
+
+    def __init__(self, host, ring, n_blocks: int, copy_stream, drop: frozenset = frozenset()):
+        super().__init__(ring, n_blocks, drop)
+        self.host = host            # pinned uint8 host tensor [R_host * BLOCK_T, F, N]
+        self.copy_stream = copy_stream
+        self.slot_free = [None] * self.ring_blocks   # event: the slot's last block has been read
+
+    def block(self, seq: int, arrival: float) -> Block:
+        import torch
+        slot = seq % self.ring_blocks
+        row = slot * BLOCK_T
+        hrow = (seq % (self.host.shape[0] // BLOCK_T)) * BLOCK_T
+        if self.slot_free[slot] is not None:
+            self.copy_stream.wait_event(self.slot_free[slot])
+        with torch.cuda.stream(self.copy_stream):
+            self.ring[row: row + BLOCK_T].copy_(self.host[hrow: hrow + BLOCK_T], non_blocking=True)
+        ready = torch.cuda.Event()
+        ready.record(self.copy_stream)
+
+        def consumed(ev, slot=slot):
+            self.slot_free[slot] = ev
+        return Block(seq, self.ring[row: row + BLOCK_T], self.ring, row, arrival, ready, consumed)
 
 
 def realtime_period(n_chans: int, sample_rate: float = 250e6) -> float:

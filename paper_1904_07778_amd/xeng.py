@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Sequence
 
@@ -350,13 +351,18 @@ class Plan:
         self.handle = None
         self.handle = xeng_plan([(s.n_inputs, s.n_chans, s.max_time_per_call) for s in self.specs],
                                 XENG_PLAN_BATCH if batch else 0, self.stream.cuda_stream)
+        # The finalizer holds the library function itself, so a plan that is
+        # still open when the interpreter shuts down is destroyed before the
+        # module's globals go away (weakref.finalize runs at exit).
+        self._finalizer = weakref.finalize(self, _lib.xeng_destroy, self.handle)
 
     def close(self):
-        if getattr(self, "handle", None):
-            xeng_destroy(self.handle)
-            self.handle = None
-
-    __del__ = close
+        """Wait for the plan's work and free it (also done when the Plan is
+        garbage-collected or at interpreter exit)."""
+        fin = getattr(self, "_finalizer", None)
+        if fin is not None and fin.alive:
+            fin()
+        self.handle = None
 
     def __enter__(self):
         return self

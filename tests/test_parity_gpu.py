@@ -2,8 +2,9 @@
 
 Integer work: every visibility must equal the oracle's exactly.  Sizes
 span several 16-row tiles with ragged edges in N and ragged tails in T; the
-full-size workloads are checked on sampled channels the oracle computes one
-by one, plus properties that hold at any size on every channel.
+full-size workloads are checked on every channel against the oracle, in the
+launch the benchmark times; the ring kernel is run at its largest time chunk
+and at the library's int32 integration limit.
 """
 import numpy as np
 import pytest
@@ -133,33 +134,108 @@ def test_integration_exact_at_int32_bound():
     assert out[0].numpy().tolist() == [[[128 * T, 0]]]
 
 
-def test_dish_scale_eight_calls_sampled_channels():
+def test_dish_scale_eight_calls_all_channels():
+    """Dish-array workload at full size: 8 calls of 16384 samples, then one
+    dump; every channel against the oracle."""
     w = synth.WORKLOADS["dish"]
     N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
     print(f"dish N={N} F={F} T={T} x {w['calls']} calls", flush=True)
     blocks = [synth.voltages(w["recipe"], w["seed"], N, F, T, block=b) for b in range(w["calls"])]
-    chans = [0, 1, 2, 511, 512, 777, 1022, 1023]
-    got = check(blocks, N, F, chans=chans, max_t=T)
+    got = check(blocks, N, F, max_t=T)
     autos = got[:, [i * (i + 1) // 2 + i for i in range(N)]]
     assert (autos[..., 1] == 0).all() and (autos[..., 0] >= 0).all()
 
 
-def test_cylinder_scale_sampled_channels():
+def test_cylinder_scale_all_channels():
+    """Cylinder workload at full size in the launch the benchmark times (one
+    fused correlate-and-dump call into a device buffer): every channel
+    against the oracle."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
     w = synth.WORKLOADS["cylinder"]
     N, F, T = w["n_inputs"], w["n_chans"], w["n_time"]
     print(f"cylinder N={N} F={F} T={T}", flush=True)
     v = synth.voltages(w["recipe"], w["seed"], N, F, T)
-    got, n = run_engine([v], N, F)
-    assert n == T
-    chans = [0, 1, 255, 256, 511, 512, 513, 1000, 1022, 1023]
-    for f in chans:
-        want = oracle.correlate(np.ascontiguousarray(v[:, f:f + 1]))
-        assert np.array_equal(got[f:f + 1], want), (f, first_mismatch(got[f:f + 1], want))
+    with Plan([(N, F, T)]) as p:
+        out, n = p.correlate_dump([torch.from_numpy(v).cuda()])
+        got = out[0].cpu().numpy()
+    assert n == [T]
+    want = oracle.correlate(v)
+    assert np.array_equal(got, want), first_mismatch(got, want)
     autos = got[:, [i * (i + 1) // 2 + i for i in range(N)]]
     assert (autos[..., 1] == 0).all() and (autos[..., 0] > 0).all()
     # Eq. 3: RMS = sqrt(P / 2N) of every input on every channel lies in 2..3
     rms = np.sqrt(autos[..., 0] / (2 * T))
     assert 2.0 < rms.mean() < 3.0
+
+
+def _closed_form(re, im, T):
+    """V_ij = T x_i conj(x_j) for inputs x_i = re_i + j im_i held constant over
+    T samples: (T (a_i a_j + b_i b_j), T (b_i a_j - a_i b_j)), lower triangle."""
+    N = len(re)
+    vis = np.zeros((N * (N + 1) // 2, 2), np.int64)
+    for i in range(N):
+        for j in range(i + 1):
+            vis[i * (i + 1) // 2 + j] = (T * (re[i] * re[j] + im[i] * im[j]),
+                                         T * (im[i] * re[j] - re[i] * im[j]))
+    return vis
+
+
+@pytest.mark.parametrize("batched", [False, True], ids=["plain", "batched"])
+@pytest.mark.parametrize("N", [16, 192])
+def test_ring_kernel_at_int32_bound(N, batched):
+    """32-row-tile ring kernel at the library's integration limit: all codes
+    -8, T = 16,777,215 in one call, so every workgroup integrates the largest
+    time chunk the kernel takes (its x256-scaled sums at their headroom) and
+    the chunks meet in the accumulator by atomic adds.  Every visibility must
+    be 128 T = 2,147,483,520 (the closed form), exact."""
+    import torch
+    from paper_1904_07778_amd.xeng import XENG_MAX_INTEGRATION, Plan
+    T, F = XENG_MAX_INTEGRATION, 1
+    print(f"ring kernel int32 bound N={N} batched={batched}", flush=True)
+    v = torch.full((T, F, N), 0x88, dtype=torch.uint8, device="cuda")
+    with Plan([(N, F, T)], batch=batched) as p:
+        p.correlate([v])
+        out, n = p.dump(to_host=True)
+    del v
+    got = out[0].numpy()
+    assert n == [T]
+    want = np.broadcast_to(np.array([128 * T, 0], np.int32), got.shape)
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
+@pytest.mark.parametrize("batched", [False, True], ids=["plain", "batched"])
+def test_ring_kernel_full_chunks_extreme_codes(batched):
+    """N = 192 with 512 channels and 65536 samples: every workgroup owns one
+    channel over 32768 samples (the ring kernel's largest chunk) and two
+    chunks meet by atomic adds.  Each input holds one extreme code for the
+    whole integration (the -8 corners included), so the x256-scaled real and
+    imaginary sums grow linearly to their largest per-chunk magnitudes.
+    Checked on every channel against the closed form V_ij = T x_i conj(x_j)
+    and on two channels against the oracle."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    N, F, T = 192, 512, 65536
+    rng = np.random.default_rng(97)
+    re = rng.choice(np.array([-8, -8, 7, 7, -7, 0, 3]), size=N)
+    im = rng.choice(np.array([-8, -8, 7, -7, 0, 5]), size=N)
+    re[:4], im[:4] = [-8, 7, -8, 7], [-8, -8, 7, 7]
+    codes = synth.pack(re, im)
+    print(f"ring kernel full chunks N={N} F={F} T={T} batched={batched}", flush=True)
+    v = torch.from_numpy(codes).cuda().view(1, 1, N).expand(T, F, N).contiguous()
+    with Plan([(N, F, T)], batch=batched) as p:
+        p.correlate([v])
+        out, n = p.dump(to_host=True)
+    got = out[0].numpy()
+    assert n == [T]
+    want = _closed_form(re.astype(np.int64), im.astype(np.int64), T)
+    assert np.abs(want).max() == 128 * T                 # the -8 - 8j autos
+    want = np.broadcast_to(want.astype(np.int32), got.shape)
+    assert np.array_equal(got, want), first_mismatch(got, want)
+    vh = v[:, :2].cpu().numpy()
+    del v
+    w2 = oracle.correlate(np.ascontiguousarray(vh))
+    assert np.array_equal(got[:2], w2), first_mismatch(got[:2], w2)
 
 
 @pytest.mark.parametrize("to_host", [False, True])
