@@ -314,6 +314,22 @@ int xeng_ingest(const uint8_t *d_packets, int64_t n_packets, int32_t packet_stri
 int xeng_channelise(const int8_t *d_adc, int64_t n_samples, int32_t n_inputs, int32_t n_chans,
                     float *d_out, float *d_tables, void *hip_stream);
 
+/*
+ * xeng_channelise_noalloc - xeng_channelise for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same computation and arguments without
+ * d_tables.  The filter and twiddle tables go to a scratch array inside the
+ * library, one per GPU, of 4 * 2048 + 2048 floats (40 KB, enough for the
+ * largest spectrum, F = 1024), held until the process ends; the call itself
+ * allocates nothing.  Every call on a GPU rewrites that GPU's array before
+ * reading it, so calls that overlap on one GPU (on different streams) race
+ * and must not be issued.  Errors: as xeng_channelise (EINVAL also for F
+ * beyond the scratch size), EDEVICE if the scratch address cannot be
+ * obtained.
+ */
+int xeng_channelise_noalloc(const int8_t *d_adc, int64_t n_samples, int32_t n_inputs, int32_t n_chans,
+                            float *d_out, void *hip_stream);
+
 /* Spectra produced from n_samples samples: n_samples / 2F - 3 (>= 0); -1 on bad sizes. */
 int64_t xeng_channelise_spectra(int64_t n_samples, int32_t n_chans);
 

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/xeng.h"
 
 namespace xeng {
@@ -182,8 +184,11 @@ extern "C" int64_t xeng_channelise_table_floats(int32_t n_chans) {
   return (int64_t)xeng::TAPS * 2 * n_chans + 2 * n_chans;  // h[4L] + L/2 complex twiddles
 }
 
-extern "C" int xeng_channelise(const int8_t* d_adc, int64_t n_samples, int32_t n_inputs, int32_t n_chans,
-                               float* d_out, float* d_tables, void* hip_stream) {
+namespace xeng {
+namespace {
+
+int channelise_impl(const int8_t* d_adc, int64_t n_samples, int32_t n_inputs, int32_t n_chans, float* d_out,
+                    float* d_tables, void* hip_stream) {
   const int L = 2 * n_chans;
   const int log2L = xeng::log2_exact(L);
   if (!d_adc || !d_tables || n_inputs < 2 || n_inputs % 2 || n_chans < 8 || L > xeng::MAX_L ||
@@ -210,4 +215,48 @@ extern "C" int xeng_channelise(const int8_t* d_adc, int64_t n_samples, int32_t n
                        reinterpret_cast<float2*>(d_out));
   }
   return hipGetLastError() == hipSuccess ? XENG_OK : XENG_EDEVICE;
+}
+
+// Table scratch of the allocation-free entry point: one array per GPU, for
+// the largest spectrum (F = 1024: 4 * 2F + 2F floats), held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address, per device, comes from hipGetSymbolAddress on the first call made
+// with that device current.
+constexpr int SCRATCH_FLOATS = TAPS * MAX_L + MAX_L;
+static __device__ __align__(256) float scratch[SCRATCH_FLOATS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+float* scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (null on failure).
+float* scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    float* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    scratch_ptr[dev] = ptr;
+  }
+  return scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace xeng
+
+extern "C" int xeng_channelise(const int8_t* d_adc, int64_t n_samples, int32_t n_inputs, int32_t n_chans,
+                               float* d_out, float* d_tables, void* hip_stream) {
+  return xeng::channelise_impl(d_adc, n_samples, n_inputs, n_chans, d_out, d_tables, hip_stream);
+}
+
+extern "C" int xeng_channelise_noalloc(const int8_t* d_adc, int64_t n_samples, int32_t n_inputs,
+                                       int32_t n_chans, float* d_out, void* hip_stream) {
+  if (n_chans < 1 || xeng_channelise_table_floats(n_chans) > xeng::SCRATCH_FLOATS) return XENG_EINVAL;
+  float* tables = xeng::scratch_on_current_device();
+  if (!tables) return XENG_EDEVICE;
+  return xeng::channelise_impl(d_adc, n_samples, n_inputs, n_chans, d_out, tables, hip_stream);
 }

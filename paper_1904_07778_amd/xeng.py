@@ -75,6 +75,8 @@ _lib.xeng_ingest.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
 _lib.xeng_ingest.restype = ctypes.c_int
 _lib.xeng_channelise.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
 _lib.xeng_channelise.restype = ctypes.c_int
+_lib.xeng_channelise_noalloc.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P]
+_lib.xeng_channelise_noalloc.restype = ctypes.c_int
 _lib.xeng_channelise_spectra.argtypes = [ctypes.c_int64, ctypes.c_int32]
 _lib.xeng_channelise_spectra.restype = ctypes.c_int64
 _lib.xeng_channelise_table_floats.argtypes = [ctypes.c_int32]
@@ -298,6 +300,11 @@ def ingest(packets, mcnt0: int, n_blocks: int, n_boards: int, n_chans: int, xid:
 def xeng_channelise(adc, n_samples: int, n_inputs: int, n_chans: int, out, tables, stream=None) -> None:
     s = getattr(stream, "cuda_stream", stream)
     _check(_lib.xeng_channelise(_ptr(adc), n_samples, n_inputs, n_chans, _ptr(out), _ptr(tables), s))
+
+
+def xeng_channelise_noalloc(adc, n_samples: int, n_inputs: int, n_chans: int, out, stream=None) -> None:
+    s = getattr(stream, "cuda_stream", stream)
+    _check(_lib.xeng_channelise_noalloc(_ptr(adc), n_samples, n_inputs, n_chans, _ptr(out), s))
 
 
 def channelise(adc, n_chans: int, out=None, tables=None, stream=None):
