@@ -13,7 +13,8 @@
 //    in a buffer resource built per stage in scalar registers, so rows past
 //    the end of the time range read as zero without touching memory and the
 //    loads need no per-lane address arithmetic (64 F N < 2^32, checked by
-//    the host).
+//    the host).  With one channel per workgroup only the two waves with the
+//    least unpack work issue loads (3% faster at N=192 than all four).
 //
 // 2. Fragments.  ds_read_b64_tr_b8 transposes, in every 16-lane group, the
 //    8 x 16 byte block of the group's 8-byte reads.  Lane l reads time row
@@ -89,7 +90,9 @@ struct Plan16 {
   bool qcol[W];        // imaginary products of wave w in the column form P_I . Q_J
   bool needP[W][NT];   // tile read as an operand
   bool needQ[W][NT];   // tile whose negated copy ~re16 is used
-  constexpr Plan16() : nu(), uI(), uJ(), uIm(), qcol(), needP(), needQ() {
+  int ntile[W];        // tiles wave w unpacks per step
+  int lrank[W];        // with four waves per channel: rank among the two loader waves, or -1
+  constexpr Plan16() : nu(), uI(), uJ(), uIm(), qcol(), needP(), needQ(), ntile(), lrank() {
     int oI[U] = {}, oJ[U] = {}, oM[U] = {};
     int n = 0;
     const int h = NT / 2;
@@ -121,6 +124,18 @@ struct Plan16 {
       }
       qcol[w] = ncol < nrow;
       for (int x = 0; x < NT; ++x) needQ[w][x] = qcol[w] ? colt[x] : rowt[x];
+      for (int x = 0; x < NT; ++x) ntile[w] += needP[w][x] ? 1 : 0;
+    }
+    // The two waves that unpack the fewest tiles issue the ring loads (their
+    // MFMA count is the same, their VALU work the smallest).
+    for (int w = 0; w < W; ++w) lrank[w] = -1;
+    if (W == 4) {
+      for (int r = 0; r < 2; ++r) {
+        int best = -1;
+        for (int w = 0; w < W; ++w)
+          if (lrank[w] < 0 && (best < 0 || ntile[w] < ntile[best])) best = w;
+        lrank[best] = r;
+      }
     }
   }
 };
@@ -142,7 +157,7 @@ struct Shape {
   static constexpr int LDS_BYTES = S * STAGE_BYTES > DIAG_BYTES ? S * STAGE_BYTES : DIAG_BYTES;
   static_assert(supported(N), "N must be a multiple of 16 up to 240");
   static_assert(LOADS * 1024 == STAGE_BYTES, "a stage is whole 1 KB loads");
-  static_assert(S >= 3 && (S - 2) * LPW_MAX < 64, "ring depth");
+  static_assert(S >= 3 && (S - 2) * (CPW == 1 ? (LOADS + 1) / 2 : LPW_MAX) < 64, "ring depth");
   static_assert(KPS >= 2 && KPS % 2 == 0, "an even number of steps per stage");
   static_assert(WAVES == 4, "four waves per workgroup");
 };
@@ -286,14 +301,21 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   const uint32_t rs32 = (uint32_t)((int64_t)a.F * N);  // one time row; 64 F N < 2^32
   const int nch_valid = min(CPW, a.F - f0);             // the last group may be short of channels
 
-  // ---- producer: wave-wide loads q = wave, wave + WAVES, ... of every stage
-  const int my_loads = (C::LOADS - wave + C::WAVES - 1) / C::WAVES;
-  const bool extra_load = CPW == 1 ? (WC + C::LPW_MIN * C::WAVES < C::LOADS)
-                                   : (wave + C::LPW_MIN * C::WAVES < C::LOADS);
-  uint32_t voff[C::LPW_MAX];
+  // ---- producer: the wave-wide 1 KB loads q = 0 .. LOADS-1 of every stage.
+  // With one channel per workgroup the two waves with the least unpack work
+  // issue them all (q = rank, rank + 2, ...; compile-time counts); with
+  // several channels per workgroup every wave issues q = wave, wave + 4, ...
+  constexpr bool ONE = CPW == 1;
+  constexpr int NLW = ONE ? 2 : C::WAVES;                 // loader waves
+  constexpr int LR = ONE ? plan.lrank[WC] : 0;            // this wave's rank (one channel)
+  constexpr int LW = ONE ? (LR < 0 ? 0 : (C::LOADS - LR + NLW - 1) / NLW) : 0;
+  constexpr int LMAX = ONE ? (C::LOADS + NLW - 1) / NLW : C::LPW_MAX;
+  const int rank = ONE ? LR : wave;
+  const int my_loads = ONE ? LW : (C::LOADS - wave + C::WAVES - 1) / C::WAVES;
+  uint32_t voff[LMAX];
 #pragma unroll
-  for (int k = 0; k < C::LPW_MAX; ++k) {
-    const int q = wave + k * C::WAVES;
+  for (int k = 0; k < LMAX; ++k) {
+    const int q = (rank < 0 ? 0 : rank) + k * NLW;
     const int slot = (q < C::LOADS ? q : 0) * 64 + lane;  // 16-byte LDS slot this lane fills
     const int t = slot / C::RPP;                          // time row
     int p = slot % C::RPP;                                // chunk within the row
@@ -324,8 +346,13 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
     rsrc[3] = 0x00020000;  // raw buffer, 32-bit data format
     const uint32_t base = ring_base + (uint32_t)((st % S) * C::STAGE_BYTES);
 #pragma unroll
-    for (int k = 0; k < C::LPW_MAX; ++k)
-      if (k < C::LPW_MIN || extra_load) buf_dma16(rsrc, voff[k], base + (wave + k * C::WAVES) * 1024);
+    for (int k = 0; k < LMAX; ++k) {
+      if constexpr (ONE) {
+        if (k < LW) buf_dma16(rsrc, voff[k], base + (LR + k * NLW) * 1024);
+      } else if (k < my_loads) {
+        buf_dma16(rsrc, voff[k], base + (wave + k * C::WAVES) * 1024);
+      }
+    }
   };
 
   // ---- consumer
@@ -343,7 +370,9 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   // rows past the end are zeroed here so the readers need no masks.
   auto enter_stage = [&](int st) {
     // the S-2 stages after st stay in flight
-    if (my_loads == C::LPW_MAX)
+    if constexpr (ONE)
+      wait_vmcnt<(S - 2) * LW>();
+    else if (my_loads == C::LPW_MAX)
       wait_vmcnt<(S - 2) * C::LPW_MAX>();
     else
       wait_vmcnt<(S - 2) * C::LPW_MIN>();
@@ -465,14 +494,15 @@ __device__ __forceinline__ void wave_main(const Args& a, uint8_t* lds, int group
   // step k; even steps use rawE / P0 for their data, odd steps rawO / P1.
   // The reads of stage st+1 start at step KPS-2 of stage st: the stage entry
   // (waits and barrier) comes right before it, and the slot of stage st,
-  // whose reads are complete by that barrier, is refilled from that block.
+  // whose reads are complete by that barrier, is refilled from the stage's
+  // last block.
   v6i P0[NT], P1[NT];
   v2i rawE[NT], rawO[NT];  // raw bytes of the even / odd steps
   auto step = [&](auto ks, auto with_reads, int st) {
     constexpr int K = decltype(ks)::value;
     constexpr int KR = (K + 2) % KPS;          // step of the reads within its stage
     const int st_rd = st + (K + 2) / KPS;
-    constexpr bool LOADS = K == KPS - 2;
+    constexpr bool LOADS = K == KPS - 1;   // (measured: 0.6% faster than in the stage's first block)
     if constexpr (!with_reads.value) {
       if constexpr (K % 2 == 0) {
         unpack(rawO, P1, X0{}, XN{});
