@@ -74,7 +74,8 @@ def log(msg: str) -> None:
 
 # sources of the timed kernels (the 16-row-tile ring kernel and its
 # instantiations); their counters go stale when any of them changes
-KERNEL_SOURCES = ("xcorr.hpp", "xcorr16.hpp", "k_x16_a.hip", "k_x16_c.hip")
+KERNEL_SOURCES = ("xcorr.hpp", "xcorr16.hpp", "xcorr32.hpp", "k_x16_a.hip", "k_x16_c.hip", "k_x32_a.hip",
+                  "batch.hpp", "k_batch.hip", "k_dump.hip", "xeng.hip")
 
 
 def kernel_source_hash() -> str:
@@ -150,6 +151,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--settle-seconds", type=float, default=1.0,
                     help="untimed run of the step before the warm-up (plain workloads)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="batch: load the autotuner's choices from this file if it exists, else tune and save")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="batch: run warm-up + steps batched calls only (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -256,15 +261,27 @@ def bench_plain(args) -> int:
     torch.cuda.synchronize()
     log(f"settled ({n_settle} steps in {time.perf_counter() - t_settle:.1f} s), warmup {args.warmup} done")
 
+    # Timed region: K steps back to back, bracketed by one pair of HIP events
+    # on the engine's stream (an event pair around every call adds a few
+    # microseconds of device time per event to the interval it measures).
+    e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    e_start.record(stream)
+    for k in range(args.steps):
+        step()
+    e_end.record(stream)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    dev_mean = e_start.elapsed_time(e_end) / args.steps      # device ms per step, launch gaps included
+    log(f"timed {args.steps} steps in {t_total:.3f} s ({dev_mean:.4f} ms per step on the device)")
+    # Spread: the same steps again with an event pair around every engine call
     ev = [[[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(calls)]
           for _ in range(args.steps)]
     torch.cuda.synchronize()
-    t_start = time.perf_counter()
     for k in range(args.steps):
         step(ev[k])
     torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    log(f"timed {args.steps} steps in {t_total:.3f} s")
     call_ms = np.array([[a.elapsed_time(b) for a, b in e] for e in ev])   # [steps][calls]
     step_dev_ms = call_ms.sum(axis=1)
 
@@ -284,7 +301,6 @@ def bench_plain(args) -> int:
     value = cmac_per_step / (ms_per_step / 1e3)
     in_bytes, out_bytes = calls * T * F * N, F * nbl * 8
     alg_bytes = in_bytes + out_bytes
-    dev_mean = float(step_dev_ms.mean())
     hbm_bound = 4 * (N + 1) < PEAK_INT8_TOPS / PEAK_HBM_GBS * 1e3
     if hbm_bound:
         achieved = alg_bytes / (dev_mean / 1e3) / 1e9
@@ -297,7 +313,7 @@ def bench_plain(args) -> int:
     roof.update({"traffic": measured_traffic(name, calls), "algorithmic_bytes": alg_bytes,
                  "hbm_gbs_algorithmic": alg_bytes / (dev_mean / 1e3) / 1e9,
                  "int8_tops": cmac_per_step * OPS_PER_CMAC / (dev_mean / 1e3) / 1e12,
-                 "time": "mean of the per-step sums of the engine calls' HIP-event durations"})
+                 "time": "device time of the K timed steps (one HIP event pair on the engine stream) / K"})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -325,12 +341,10 @@ def bench_plain(args) -> int:
                             f"{calls - 1} xeng_correlate calls, then xeng_correlate_dump"),
                    "settle_s": args.settle_seconds, "autotuned_ms_per_call": tuned_ms},
         "kernel_ms": dev_mean,
-        "kernel_ms_median": float(np.median(step_dev_ms)),
-        "kernel_ms_min": float(step_dev_ms.min()),
-        "kernel_ms_max": float(step_dev_ms.max()),
+        "step_event_ms": {"median": float(np.median(step_dev_ms)), "min": float(step_dev_ms.min()),
+                          "mean": float(step_dev_ms.mean()), "max": float(step_dev_ms.max()),
+                          "note": "a second pass of K steps with an event pair around every engine call"},
         "int8_mfma_frac_of_step": value * OPS_PER_CMAC / (PEAK_INT8_TOPS * 1e12),
-        "int8_mfma_frac_kernel_median": cmac_per_step * OPS_PER_CMAC / (float(np.median(step_dev_ms)) / 1e3)
-                                        / (PEAK_INT8_TOPS * 1e12),
         "rtf": value / (nbl * REALTIME_SPECTRA_PER_S),
         "rtf_full_matrix_reading": value / (nbl * REALTIME_SPECTRA_PER_S) / 2,
         "roofline": roof,
@@ -366,16 +380,31 @@ def bench_batch(args) -> int:
     cmac = sum(n * (n + 1) // 2 * f * t for n, f, t in shapes)
     in_bytes = sum(n * f * t for n, f, t in shapes)
     out_bytes = sum(n * (n + 1) // 2 * f * 8 for n, f, t in shapes)
+    from paper_1904_07778_amd import xeng as X
     stream = torch.cuda.Stream()
+    cached = bool(args.tune_cache) and os.path.exists(args.tune_cache)
+    if cached:
+        X.xeng_tune_cache_load(args.tune_cache)          # plans start from the cached choices
+        log(f"tuning cache loaded from {args.tune_cache}")
     batched = Plan(shapes, stream=stream)
     plain = [Plan([sh], stream=stream) for sh in shapes]
     torch.cuda.synchronize()
-    log("autotuning")
-    tb = batched.autotune(dev, reps=3)
-    tp = sum(p.autotune([v], reps=3) for p, v in zip(plain, dev))
-    log(f"autotuned: batched {tb:.3f} ms, plain sum {tp:.3f} ms")
+    tb = tp = None
+    if not cached:
+        log("autotuning")
+        tb = batched.autotune(dev, reps=3)
+        tp = sum(p.autotune([v], reps=3) for p, v in zip(plain, dev))
+        log(f"autotuned: batched {tb:.3f} ms, plain sum {tp:.3f} ms")
+        if args.tune_cache:
+            X.xeng_tune_cache_save(args.tune_cache)
     out_b = [batched.new_output(k) for k in range(len(shapes))]
     out_p = [p.new_output(0) for p in plain]
+    if args.batched_only:      # counter runs: the batched steps alone
+        for _ in range(args.warmup + args.steps):
+            batched.correlate_dump(dev, out=out_b)
+        torch.cuda.synchronize()
+        log(f"ran {args.warmup + args.steps} batched steps")
+        return 0
 
     # both forms integrate and dump in one call per plan (xeng_correlate_dump)
     def step_batched():
@@ -408,17 +437,27 @@ def bench_batch(args) -> int:
                                     "T in {2048, 4096, 8192} (seed 4), 4+4-bit complex",
                         "arrays": shapes,
                         "step": "batched correlate + dump of all arrays in one call (xeng_correlate_dump)"})
+    # the mix's combined bound: its bytes at 8 TB/s or its int8 work at 5 POP/s
+    t_hbm = (in_bytes + out_bytes) / (PEAK_HBM_GBS * 1e9)
+    t_mfma = cmac * OPS_PER_CMAC / (PEAK_INT8_TOPS * 1e12)
+    hbm_dom = t_hbm >= t_mfma
+    achieved = ((in_bytes + out_bytes) / (dev_ms_b / 1e3) / 1e9 if hbm_dom
+                else cmac * OPS_PER_CMAC / (dev_ms_b / 1e3) / 1e12)
+    peak = PEAK_HBM_GBS if hbm_dom else PEAK_INT8_TOPS
     rec.update({
         "plain_value": cmac / (ms_p / 1e3), "plain_ms_per_step": ms_p,
         "speedup_vs_plain": ms_p / ms_b, "identical_to_plain": same,
         "device_ms_per_step": dev_ms_b, "plain_device_ms_per_step": dev_ms_p,
-        "autotuned_ms": {"batched": tb, "plain_sum": tp},
+        "device_speedup_vs_plain": dev_ms_p / dev_ms_b,
+        "autotuned_ms": {"batched": tb, "plain_sum": tp, "from_cache": cached},
         "int8_mfma_frac_of_step": cmac * OPS_PER_CMAC / (ms_b / 1e3) / (PEAK_INT8_TOPS * 1e12),
-        "roofline": {"bound": "hbm", "achieved": (in_bytes + out_bytes) / (dev_ms_b / 1e3) / 1e9,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": (in_bytes + out_bytes) / (dev_ms_b / 1e3) / 1e9 / PEAK_HBM_GBS,
-                     "traffic": None, "algorithmic_bytes": in_bytes + out_bytes,
-                     "note": "whole step (batch kernel + dump kernel) on the engine stream"},
+        "roofline": {"bound": "hbm" if hbm_dom else "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "GB/s" if hbm_dom else "TOP/s", "frac": achieved / peak,
+                     "traffic": measured_traffic("batch"), "algorithmic_bytes": in_bytes + out_bytes,
+                     "combined_bound_ms": max(t_hbm, t_mfma) * 1e3,
+                     "note": "whole step (the graph: batch kernel, any own launches, carry-over copies) "
+                             "on the engine stream, against the mix's bytes at 8 TB/s or its int8 work "
+                             "at 5 POP/s, whichever is longer"},
         "cpu_baseline": None,
     })
     print(json.dumps(rec), flush=True)

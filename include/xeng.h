@@ -213,16 +213,35 @@ int64_t xeng_accumulator_bytes(int32_t n_inputs, int32_t n_chans);
  *   reps                calls timed per candidate (>= 1).
  *   best_ms             optional out: mean time of one call with the choice.
  * Batched plan: the work-item granularity of the persistent launch (about
- * 1, 2, 4 or 8 items per compute unit; items are cut along time).  Plain
- * plan, per array: the tile shape (32-row tiles of the ring kernel, N a
- * multiple of 16, or 16-row tiles of the staging kernel) and the number of
- * workgroups per compute unit that the time split aims for.  The choice is
- * kept by the plan for later calls.  Every accumulator must be freshly dumped
- * (or never used); the trial sums are discarded and the accumulators are zero
- * on return.  Synchronous.  Errors: EINVAL, EDEVICE, ESTATE.
+ * 1, 2, 4 or 8 items per compute unit; items are cut along time), then per
+ * array, largest first, whether it runs as items of the persistent launch
+ * (16-row tiles) or as a plain launch of its own inside the same graph, with
+ * the tile shape and time split that suit it.  Plain plan, per array: the
+ * tile shape (16-row tiles of the 16x16x64 ring kernel, 32-row tiles of the
+ * 32x32x32 ring kernel, both for N a multiple of 16, or 16-row tiles of the
+ * staging kernel) and the number of workgroups per compute unit that the
+ * time split aims for.  The choice is kept by the plan for later calls and
+ * entered in the process's tuning cache (xeng_tune_cache_save), which new
+ * plans of the same GPU architecture, kind, N and power-of-two buckets of F
+ * and of max_time_per_call start from.  Every accumulator must be freshly
+ * dumped (or never used); the trial sums are discarded and the accumulators
+ * are zero on return.  Synchronous.  Errors: EINVAL, EDEVICE, ESTATE.
  */
 int xeng_autotune(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64_t *n_time,
                   int32_t reps, float *best_ms);
+
+/*
+ * xeng_tune_cache_save / xeng_tune_cache_load / xeng_tune_cache_clear - the
+ * process-wide tuning cache of xeng_autotune as a text file (one choice per
+ * line: architecture, batched, N, log2 F bucket, log2 T bucket, tile shape,
+ * time split, own launch), so a later process skips the timing.  Loading
+ * adds to (and overrides) what the cache holds; plans made afterwards use
+ * it.  Errors: EINVAL (null path, file not readable or writable; for load
+ * also malformed lines, which are skipped).
+ */
+int xeng_tune_cache_save(const char *path);
+int xeng_tune_cache_load(const char *path);
+int xeng_tune_cache_clear(void);
 
 /*
  * xeng_requantize - equaliser / 4-bit requantiser of the F stage (Sec. 2.1),

@@ -16,8 +16,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/xeng.h"
@@ -40,13 +43,55 @@ struct ArrayState {
                        // zeroes it first when it must add atomically)
   const KernelInfo* k = nullptr;  // kernel of the plain launch
   int split = 2;                  // plain launch: aim for split * n_cu workgroups
+  bool own_launch = false;        // batched plan: a plain launch of its own inside the
+                                  // graph instead of items of the persistent launch
 };
+
+// ---- tuning cache: the launch shapes the autotuner picked, by GPU
+// architecture, plan kind, N and the power-of-two buckets of F and T, for the
+// whole process (xeng_tune_cache_save / _load write and read it as text).
+enum KernelKind { KIND_X16 = 0, KIND_X32 = 1, KIND_STAGE = 2 };
+
+const KernelInfo* kernel_of(int kind, int32_t n) {
+  switch (kind) {
+    case KIND_X16: return xeng::x16_kernel(n);
+    case KIND_X32: return xeng::x32_kernel(n);
+    case KIND_STAGE: return xeng::stage_kernel((n + 15) / 16);
+    default: return nullptr;
+  }
+}
+
+int kind_of(const KernelInfo* k, int32_t n) {
+  if (k == xeng::x16_kernel(n)) return KIND_X16;
+  if (k == xeng::x32_kernel(n)) return KIND_X32;
+  return KIND_STAGE;
+}
+
+int bucket(int64_t v) {  // ceil(log2 v)
+  int b = 0;
+  while (((int64_t)1 << b) < v && b < 62) ++b;
+  return b;
+}
+
+struct TuneKey {
+  std::string arch;
+  int batched, n, fb, tb;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, batched, n, fb, tb) < std::tie(o.arch, o.batched, o.n, o.fb, o.tb);
+  }
+};
+struct TuneVal {
+  int kind, split, own;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
 
 }  // namespace
 
 struct xeng_plan_s {
   int device = 0;
   int n_cu = 256;
+  std::string arch;       // gcnArchName of the device (tuning-cache key)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool dead = false;
@@ -130,10 +175,30 @@ const KernelInfo* default_kernel(const xeng_array_desc& d) {
   return xeng::stage_kernel((n + 15) / 16);
 }
 
+// The cached choice for an array of this plan, if the autotuner has made one.
+void apply_cached(const xeng_plan_t* p, ArrayState& s, int64_t T) {
+  const TuneKey key{p->arch, p->batched ? 1 : 0, s.d.n_inputs, bucket(s.d.n_chans), bucket(T)};
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return;
+  const KernelInfo* k = kernel_of(it->second.kind, s.d.n_inputs);
+  if (!kernel_fits(k, s.d)) return;
+  s.k = k;
+  s.split = it->second.split;
+  s.own_launch = p->batched && it->second.own;
+}
+
+void record_choice(const xeng_plan_t* p, const ArrayState& s, int64_t T) {
+  const TuneKey key{p->arch, p->batched ? 1 : 0, s.d.n_inputs, bucket(s.d.n_chans), bucket(T)};
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[key] = TuneVal{kind_of(s.k, s.d.n_inputs), s.split, s.own_launch ? 1 : 0};
+}
+
 int init_slot(xeng_plan_t* p, ArrayState& s, const xeng_array_desc& d) {
   s = ArrayState{};
   s.d = d;
   s.k = default_kernel(d);
+  apply_cached(p, s, d.max_time_per_call);
   s.acc_bytes = (size_t)d.n_chans * nbl_of(d.n_inputs) * 2 * sizeof(int32_t);
   hipError_t e = hipMalloc(&s.acc, s.acc_bytes);
   if (e != hipSuccess) {
@@ -235,7 +300,7 @@ int record_batched(xeng_plan_t* p, const uint8_t* const* v, const int64_t* n_tim
   for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a) {
     const ArrayState& s = p->arrays[a];
     if (!s.active || n_time[a] == 0) continue;
-    if (!xeng::batch::supports(s.d.n_inputs) || s.k != xeng::x16_kernel(s.d.n_inputs)) {
+    if (s.own_launch || !xeng::batch::supports(s.d.n_inputs) || s.k != xeng::x16_kernel(s.d.n_inputs)) {
       others.push_back(a);
       continue;
     }
@@ -473,6 +538,14 @@ int xeng_plan(xeng_plan_t** out, const xeng_array_desc* arrays, int32_t n_arrays
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
       ncu > 0)
     p->n_cu = ncu;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+      p->arch = prop.gcnArchName;
+      const size_t colon = p->arch.find(':');
+      if (colon != std::string::npos) p->arch.resize(colon);
+    }
+  }
   if (hip_stream) {
     p->stream = reinterpret_cast<hipStream_t>(hip_stream);
   } else {
@@ -676,6 +749,48 @@ int xeng_autotune(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_
       }
     }
     p->batch_split = pick;
+    // Per array, largest work first: items of the persistent launch (16-row
+    // tiles), or a plain launch of its own inside the same graph with the
+    // tile shape and time split that suit it best; kept when the whole call
+    // gets faster by more than 1%.
+    std::vector<int32_t> order;
+    for (int32_t a = 0; a < (int32_t)p->arrays.size(); ++a)
+      if (p->arrays[a].active && n_time[a] > 0) order.push_back(a);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+      const ArrayState &sx = p->arrays[x], &sy = p->arrays[y];
+      return n_time[x] * sx.d.n_chans * nbl_of(sx.d.n_inputs) > n_time[y] * sy.d.n_chans * nbl_of(sy.d.n_inputs);
+    });
+    for (int32_t a : order) {
+      if (st != XENG_OK) break;
+      ArrayState& s = p->arrays[a];
+      const ArrayState keep = s;
+      ArrayState choice = s;
+      for (int kind : {KIND_X16, KIND_X32, KIND_STAGE}) {
+        const KernelInfo* k = kernel_of(kind, s.d.n_inputs);
+        if (!kernel_fits(k, s.d) || (kind != KIND_STAGE && s.d.n_inputs % 16 != 0)) continue;
+        for (int split : {1, 2}) {
+          s.k = k;
+          s.split = split;
+          s.own_launch = true;
+          float ms = 0;
+          st = trial(ms);
+          if (st != XENG_OK) break;
+          if (ms < 0.99f * best) {
+            best = ms;
+            choice = s;
+          }
+        }
+        if (st != XENG_OK) break;
+      }
+      const bool own = choice.own_launch;
+      s = keep;
+      if (own) {
+        s.k = choice.k;
+        s.split = choice.split;
+        s.own_launch = true;
+      }
+    }
+    for (int32_t a : order) record_choice(p, p->arrays[a], n_time[a]);
   } else {
     // per array: tile shape (32-row tiles of the ring kernel or 16-row tiles
     // of the staging kernel) and workgroups per CU of the time split
@@ -710,6 +825,7 @@ int xeng_autotune(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_
       s.split = pick_split;
       best += arr_best;
       if (st != XENG_OK) break;
+      if (n_time[&s - &p->arrays[0]] > 0) record_choice(p, s, n_time[&s - &p->arrays[0]]);
     }
   }
   const int z = zero_accumulators(p);
@@ -719,6 +835,48 @@ int xeng_autotune(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_
   (void)hipEventDestroy(t1);
   if (st == XENG_OK && best_ms) *best_ms = best / (float)reps;
   return st;
+}
+
+int xeng_tune_cache_save(const char* path) {
+  if (!path) return XENG_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) return XENG_EINVAL;
+  fprintf(f, "# xeng tuning cache: arch batched N log2F log2T kernel(0=16-row,1=32-row,2=staging) split own\n");
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const auto& kv : g_tune)
+      fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.arch.c_str(), kv.first.batched, kv.first.n, kv.first.fb,
+              kv.first.tb, kv.second.kind, kv.second.split, kv.second.own);
+  }
+  return fclose(f) == 0 ? XENG_OK : XENG_EINVAL;
+}
+
+int xeng_tune_cache_load(const char* path) {
+  if (!path) return XENG_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) return XENG_EINVAL;
+  char line[512];
+  int st = XENG_OK;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    char arch[128];
+    int b, n, fb, tb, kind, split, own;
+    if (sscanf(line, "%127s %d %d %d %d %d %d %d", arch, &b, &n, &fb, &tb, &kind, &split, &own) != 8 ||
+        n < 1 || n > XENG_MAX_INPUTS || kind < KIND_X16 || kind > KIND_STAGE || split < 1 || split > 64) {
+      st = XENG_EINVAL;  // malformed line: skipped, reported
+      continue;
+    }
+    g_tune[TuneKey{arch, b ? 1 : 0, n, fb, tb}] = TuneVal{kind, split, own ? 1 : 0};
+  }
+  fclose(f);
+  return st;
+}
+
+int xeng_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+  return XENG_OK;
 }
 
 int xeng_dump(xeng_plan_t* p, int32_t array, int32_t* const* dst, uint32_t flags,

@@ -75,6 +75,12 @@ _lib.xeng_ingest.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
 _lib.xeng_ingest.restype = ctypes.c_int
 _lib.xeng_channelise.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]
 _lib.xeng_channelise.restype = ctypes.c_int
+_lib.xeng_tune_cache_save.argtypes = [ctypes.c_char_p]
+_lib.xeng_tune_cache_save.restype = ctypes.c_int
+_lib.xeng_tune_cache_load.argtypes = [ctypes.c_char_p]
+_lib.xeng_tune_cache_load.restype = ctypes.c_int
+_lib.xeng_tune_cache_clear.argtypes = []
+_lib.xeng_tune_cache_clear.restype = ctypes.c_int
 _lib.xeng_channelise_noalloc.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P]
 _lib.xeng_channelise_noalloc.restype = ctypes.c_int
 _lib.xeng_channelise_spectra.argtypes = [ctypes.c_int64, ctypes.c_int32]
@@ -189,6 +195,18 @@ def xeng_autotune(plan: int, voltages: Sequence, n_time: Sequence[int], reps: in
     best = ctypes.c_float()
     _check(_lib.xeng_autotune(plan, ptrs, ts, reps, ctypes.byref(best)), plan)
     return best.value
+
+
+def xeng_tune_cache_save(path: str) -> None:
+    _check(_lib.xeng_tune_cache_save(os.fsencode(path)))
+
+
+def xeng_tune_cache_load(path: str) -> None:
+    _check(_lib.xeng_tune_cache_load(os.fsencode(path)))
+
+
+def xeng_tune_cache_clear() -> None:
+    _check(_lib.xeng_tune_cache_clear())
 
 
 def xeng_nbaselines(n: int) -> int:

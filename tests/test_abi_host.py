@@ -140,3 +140,28 @@ def test_stats_and_load_argument_checks():
 def test_correlate_dump_argument_checks():
     from paper_1904_07778_amd import xeng as X
     assert X._lib.xeng_correlate_dump(None, None, None, None, None) == X.XENG_EINVAL
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """The tuning cache reads and writes its text form without a GPU;
+    malformed lines are skipped and reported."""
+    from paper_1904_07778_amd import xeng as X
+    X.xeng_tune_cache_clear()
+    src = tmp_path / "tune.txt"
+    src.write_text("# comment\n"
+                   "gfx950 0 192 10 13 0 2 0\n"
+                   "gfx950 1 32 10 11 1 1 1\n"
+                   "gfx950 0 999 10 13 0 2 0\n"     # N out of range
+                   "garbage line\n")
+    with pytest.raises(X.XengError) as ei:
+        X.xeng_tune_cache_load(str(src))
+    assert ei.value.status == X.XENG_EINVAL
+    out = tmp_path / "saved.txt"
+    X.xeng_tune_cache_save(str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert sorted(lines) == ["gfx950 0 192 10 13 0 2 0", "gfx950 1 32 10 11 1 1 1"]
+    X.xeng_tune_cache_clear()
+    X.xeng_tune_cache_save(str(out))
+    assert [l for l in out.read_text().splitlines() if not l.startswith("#")] == []
+    with pytest.raises(X.XengError):
+        X.xeng_tune_cache_load(str(tmp_path / "missing.txt"))

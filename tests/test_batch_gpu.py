@@ -267,3 +267,43 @@ def test_batched_call_with_nothing_to_do():
     assert list(n0) == [0, 0] and list(n) == [512, 512]
     for (N, F, _), x, got in zip(shapes, b, out):
         assert np.array_equal(got.numpy(), oracle_vis([x], N, F))
+
+
+def test_cached_own_launches_in_a_batched_plan(tmp_path):
+    """Tuning-cache entries that give arrays of a batched plan plain launches
+    of their own (16-row, 32-row and staging tile shapes) inside the graph:
+    the results still equal the oracle; a plain plan picks up its cached tile
+    shape too."""
+    import torch
+    from paper_1904_07778_amd import xeng as X
+    from paper_1904_07778_amd.xeng import Plan
+    dev_arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    rng = np.random.default_rng(61)
+    shapes = [(192, 3, 700), (48, 5, 1500), (32, 4, 300), (64, 2, 1000)]
+    blocks = [rand_block(rng, T, F, N) for N, F, T in shapes]
+    # log2 buckets of F and of max_time_per_call, as the library computes them
+    bucket = lambda v: max(0, int(v - 1).bit_length())
+    lines = [f"{dev_arch} 1 192 {bucket(3)} {bucket(700)} 0 1 1",     # own launch, 16-row tiles
+             f"{dev_arch} 1 48 {bucket(5)} {bucket(1500)} 1 2 1",     # own launch, 32-row tiles
+             f"{dev_arch} 1 32 {bucket(4)} {bucket(300)} 2 1 1",      # own launch, staging kernel
+             f"{dev_arch} 0 64 {bucket(2)} {bucket(1000)} 1 4 0"]     # plain plan: 32-row tiles
+    f = tmp_path / "tune.txt"
+    f.write_text("\n".join(lines) + "\n")
+    X.xeng_tune_cache_clear()
+    X.xeng_tune_cache_load(str(f))
+    print("cached own launches", shapes, flush=True)
+    try:
+        with Plan(shapes) as p:
+            p.correlate([to_dev(b) for b in blocks])
+            out, n = p.dump(to_host=True)
+        with Plan([shapes[3]]) as q:
+            q.correlate([to_dev(blocks[3])])
+            out_plain, _ = q.dump(to_host=True)
+    finally:
+        X.xeng_tune_cache_clear()
+    torch.cuda.synchronize()
+    for (N, F, T), b, got, k in zip(shapes, blocks, out, n):
+        assert k == T
+        want = oracle_vis([b], N, F)
+        assert np.array_equal(got.numpy(), want), f"N={N}: " + first_mismatch(got.numpy(), want)
+    assert np.array_equal(out_plain[0].numpy(), oracle_vis([blocks[3]], 64, 2))
