@@ -175,6 +175,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    # Every step runs on this one stream: inputs, outputs, the engine's
+    # launches and the timing events share it, so no call waits across streams.
+    torch.cuda.set_stream(torch.cuda.Stream())
     if args.copy_calibration:
         copy_calibration()
         return 0
@@ -231,7 +234,7 @@ def bench_plain(args) -> int:
     log(f"generated in {time.perf_counter() - t0:.1f} s")
     v = [torch.from_numpy(h).cuda() for h in v_host]
 
-    stream = torch.cuda.Stream()
+    stream = torch.cuda.current_stream()
     plan = Plan([(N, F, T)], stream=stream)
     out = plan.new_output(0)
     torch.cuda.synchronize()
@@ -381,7 +384,7 @@ def bench_batch(args) -> int:
     in_bytes = sum(n * f * t for n, f, t in shapes)
     out_bytes = sum(n * (n + 1) // 2 * f * 8 for n, f, t in shapes)
     from paper_1904_07778_amd import xeng as X
-    stream = torch.cuda.Stream()
+    stream = torch.cuda.current_stream()
     cached = bool(args.tune_cache) and os.path.exists(args.tune_cache)
     if cached:
         X.xeng_tune_cache_load(args.tune_cache)          # plans start from the cached choices
@@ -531,7 +534,7 @@ def bench_stream(args) -> int:
     t_serve_h2d, srv_h2d = saturating(True)
 
     # saturating: plain loop, one launch per block per sub-array, round robin
-    stream = torch.cuda.Stream()
+    stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     for _wave in range(2):
         active = []

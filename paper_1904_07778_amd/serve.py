@@ -239,7 +239,20 @@ class Server:
     def step(self) -> bool:
         """Admit what fits, correlate every slot's ready blocks in one call,
         dump the slots whose integration is complete.  Returns whether any
-        work was issued."""
+        work was issued.
+
+        The iteration runs on the engine's stream, after the caller's current
+        stream (which wrote the blocks of a device feed); so the engine's calls
+        are in stream order and make no waits between streams."""
+        torch = self.torch
+        caller = torch.cuda.current_stream()
+        if caller == self.plan.stream:
+            return self._step()
+        self.plan.stream.wait_stream(caller)
+        with torch.cuda.stream(self.plan.stream):
+            return self._step()
+
+    def _step(self) -> bool:
         self._admit()
         if not self.slots:
             return False

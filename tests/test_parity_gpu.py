@@ -117,6 +117,36 @@ def test_dump_to_device_buffer():
         assert np.array_equal(out[0].cpu().numpy(), oracle.correlate(v))
 
 
+def test_caller_on_the_engine_stream():
+    """A caller that runs on the engine's stream gets stream order and no
+    waits across streams: one device input buffer is refilled in place between
+    calls, and every integration still equals the oracle."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    N, F, T = 64, 8, 1024
+    blocks = [synth.voltages("sources", 11, N, F, T, block=b) for b in range(3)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream), Plan([(N, F, T)], stream=stream) as p:
+        buf = torch.empty((T, F, N), dtype=torch.uint8, device="cuda")
+        out = p.new_output(0)
+        for b in blocks[:2]:
+            buf.copy_(torch.from_numpy(b).pin_memory(), non_blocking=True)
+            p.correlate([buf])
+        buf.copy_(torch.from_numpy(blocks[2]).pin_memory(), non_blocking=True)
+        p.correlate_dump([buf], out=[out])
+        got = out.cpu().numpy()
+        buf.copy_(torch.from_numpy(blocks[0]).pin_memory(), non_blocking=True)
+        p.correlate_dump([buf], out=[out])
+        got0 = out.cpu().numpy()
+    e = oracle.Engine(N, F)
+    for b in blocks:
+        e.correlate(b)
+    want, _ = e.dump()
+    assert np.array_equal(got, want), first_mismatch(got, want)
+    want0 = oracle.correlate(blocks[0])
+    assert np.array_equal(got0, want0), first_mismatch(got0, want0)
+
+
 def test_integration_exact_at_int32_bound():
     """One input, all codes -8: the auto reaches 128 * 16,777,215 = 2,147,483,520,
     the largest integration the library accepts, and must be exact."""
