@@ -15,7 +15,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <mutex>
+#include <type_traits>
 
 #include "../../include/xeng.h"
 
@@ -163,6 +165,236 @@ __global__ __launch_bounds__(CTHREADS) void channelise(const int8_t* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident form for L = 512, 1024, 2048 (F = 256, 512, 1024; the
+// paper's FFT lengths are 512 and 1024 complex points).  A workgroup takes
+// P input pairs (2 when the pair count is even, else 1), L / 8 threads per
+// pair, and a run of consecutive spectra:
+//  - thread t of a pair owns the points n = t + m L/8 (m < 8) of every
+//    stage, which are the inputs of its first radix-8 butterfly; its 32
+//    filter taps h[pL + n] and its twiddles stay in registers for the run;
+//  - the four input blocks a spectrum's filter reads slide along the run:
+//    each block of each stream is loaded once per run (one byte per point,
+//    64 consecutive bytes per wave and point), converted once, and kept in
+//    registers while the four spectra that use it are formed; the next
+//    block's loads are issued a spectrum ahead;
+//  - Stockham FFT: three radix-8 passes and, for L = 1024 / 2048, one
+//    radix-2 / radix-4 pass, butterflies in registers; between passes the
+//    points go through LDS (two buffers per pair, one barrier per exchange),
+//    with an address swizzle per exchange chosen so that neither the writes
+//    nor the reads of that exchange have bank conflicts;
+//  - Eq. 2 reads Y[k] and Y[L - k] from LDS; neighbouring lanes take the P
+//    pairs of one channel, so each store writes 16 P contiguous bytes.
+// The output is [spectrum][channel][input]: a pair owns 16 bytes of each
+// 1536-byte channel row at N = 192, and the cost of the run is in those
+// scattered stores.  Short runs (8 spectra) keep the workgroups that share
+// a 128-byte line close in time, so that the line is completed in L2 before
+// it is written back; each XCD takes a contiguous range of work items (pair
+// group fastest).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// 4-point forward DFT in place
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
+  const float2 s13 = cadd(x1, x3);
+  const float2 d13 = make_float2(x1.y - x3.y, x3.x - x1.x);  // -i (x1 - x3)
+  x0 = cadd(s02, s13);
+  x2 = csub(s02, s13);
+  x1 = cadd(d02, d13);
+  x3 = csub(d02, d13);
+}
+
+// 8-point forward DFT in place, natural order: X[2r] = DFT4(a_n + a_n+4)[r],
+// X[2r+1] = DFT4((a_n - a_n+4) e^{-2 pi i n / 8})[r]
+__device__ __forceinline__ void dft8(float2 (&a)[8]) {
+  constexpr float R = 0.70710678118654752440f;
+  float2 e0 = cadd(a[0], a[4]), e1 = cadd(a[1], a[5]), e2 = cadd(a[2], a[6]), e3 = cadd(a[3], a[7]);
+  float2 o0 = csub(a[0], a[4]), o1 = csub(a[1], a[5]), o2 = csub(a[2], a[6]), o3 = csub(a[3], a[7]);
+  o1 = make_float2((o1.x + o1.y) * R, (o1.y - o1.x) * R);      // x (1 - i) / sqrt 2
+  o2 = make_float2(o2.y, -o2.x);                               // x (-i)
+  o3 = make_float2((o3.y - o3.x) * R, -(o3.x + o3.y) * R);     // x (-1 - i) / sqrt 2
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  a[0] = e0; a[2] = e1; a[4] = e2; a[6] = e3;
+  a[1] = o0; a[3] = o1; a[5] = o2; a[7] = o3;
+}
+
+// LDS address swizzles, one per exchange (bijections on [0, L); the second
+// pads one entry per 32)
+struct SwzA { __device__ int operator()(int i) const { return i ^ ((i >> 3) & 31); } };
+struct SwzB { __device__ int operator()(int i) const { return i + (i >> 5); } };
+struct SwzY { __device__ int operator()(int i) const { return i ^ ((i >> 2) & 1); } };
+
+constexpr int REG_CHUNK = 8;   // spectra per workgroup run
+
+template <int L, int P>
+__global__ __launch_bounds__(P * L / 8) void channelise_reg(const int8_t* __restrict__ adc, int64_t n_samples,
+                                                         int n_inputs, int n_spec, int chunk,
+                                                         const float* __restrict__ tab,
+                                                         float4* __restrict__ out) {
+  constexpr int TH = L / 8, F = L / 2, RL = L / 512;     // RL: radix of the last pass (1: none)
+  constexpr int EX = RL > 1 ? 4 : 3;                      // LDS exchanges per spectrum
+  constexpr int BUF = L + L / 32 + 8;
+  __shared__ float2 lds_all[2][P][BUF];
+  const int pp = threadIdx.x / TH;
+  const int t = threadIdx.x % TH;
+  const int pairs = n_inputs / 2;
+  const int groups = pairs / P;
+  // work item (pair group fastest): each XCD takes a contiguous range
+  const int64_t total = gridDim.x, b = blockIdx.x;
+  const int64_t xq = total / 8, xr = total % 8, xcd = b % 8;
+  const int64_t w = xcd * xq + (xcd < xr ? xcd : xr) + b / 8;
+  const int qg = (int)(w % groups);
+  const int q = qg * P + pp;
+  const int s0 = (int)(w / groups) * chunk;
+  const int s1 = min(n_spec, s0 + chunk);
+  const float2* tw = reinterpret_cast<const float2*>(tab + 4 * L);
+
+  float hr[4][8];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) hr[p][m] = tab[p * L + t + m * TH];
+  float2 w2[8], w3[8], wl[8];
+#pragma unroll
+  for (int m = 1; m < 8; ++m) {
+    w2[m] = twiddle(tw, (m * (t & 7) * (L / 64)) & (L - 1), L);     // pass 2: Ns = 8
+    w3[m] = twiddle(tw, (m * (t & 63) * (L / 512)) & (L - 1), L);   // pass 3: Ns = 64
+  }
+  if constexpr (RL == 4) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int m = 1; m < 4; ++m) wl[4 * i + m] = twiddle(tw, (m * (t + i * TH)) & (L - 1), L);
+  } else if constexpr (RL == 2) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) wl[i] = twiddle(tw, t + i * TH, L);
+  }
+
+  const int8_t* xs[2] = {adc + (int64_t)(2 * q) * n_samples + t, adc + (int64_t)(2 * q + 1) * n_samples + t};
+  float xw[4][2][8];   // window slot (block - s0) mod 4, stream, point
+  int inc[2][8];       // loads of the next block
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) xw[b][c][m] = (float)xs[c][(int64_t)(s0 + b) * L + m * TH];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) inc[c][m] = xs[c][(int64_t)(s0 + 3) * L + m * TH];
+
+  auto exchange_write = [&](int buf, auto swz, const float2 (&a)[8], auto index) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) lds_all[buf][pp][swz(index(m))] = a[m];
+  };
+  auto exchange_read = [&](int buf, auto swz, float2 (&a)[8]) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) a[m] = lds_all[buf][pp][swz(t + m * TH)];
+  };
+  auto twiddled_dft8 = [&](float2 (&a)[8], const float2 (&wv)[8]) {
+#pragma unroll
+    for (int m = 1; m < 8; ++m) a[m] = cmul(a[m], wv[m]);
+    dft8(a);
+  };
+
+  auto spectrum = [&](auto U_, int s) {
+    constexpr int U = decltype(U_)::value;
+    constexpr int E0 = (U * EX) & 1;                    // buffer of this spectrum's first exchange
+    // block s + 3 has arrived; issue block s + 4 for the next spectrum
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) xw[(U + 3) & 3][c][m] = (float)inc[c][m];
+    if (s + 1 < s1) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) inc[c][m] = xs[c][(int64_t)(s + 4) * L + m * TH];
+    }
+    // Eq. 1 after the polyphase filter: y = v_2q + j v_2q+1
+    float2 a[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      float v0 = hr[0][m] * xw[U & 3][0][m], v1 = hr[0][m] * xw[U & 3][1][m];
+#pragma unroll
+      for (int p = 1; p < 4; ++p) {
+        v0 = fmaf(hr[p][m], xw[(U + p) & 3][0][m], v0);
+        v1 = fmaf(hr[p][m], xw[(U + p) & 3][1][m], v1);
+      }
+      a[m] = make_float2(v0, v1);
+    }
+    // pass 1 (Ns = 1): outputs to 8 t + m
+    dft8(a);
+    exchange_write(E0, SwzA{}, a, [&](int m) { return 8 * t + m; });
+    __syncthreads();
+    exchange_read(E0, SwzA{}, a);
+    // pass 2 (Ns = 8)
+    twiddled_dft8(a, w2);
+    exchange_write(E0 ^ 1, SwzA{}, a, [&](int m) { return 8 * (t & ~7) + (t & 7) + 8 * m; });
+    __syncthreads();
+    exchange_read(E0 ^ 1, SwzA{}, a);
+    // pass 3 (Ns = 64)
+    twiddled_dft8(a, w3);
+    int ybuf;
+    if constexpr (RL == 1) {           // Y in natural order
+      exchange_write(E0, SwzY{}, a, [&](int m) { return 8 * (t & ~63) + (t & 63) + 64 * m; });
+      ybuf = E0;
+    } else {
+      exchange_write(E0, SwzB{}, a, [&](int m) { return 8 * (t & ~63) + (t & 63) + 64 * m; });
+      __syncthreads();
+      exchange_read(E0, SwzB{}, a);
+      // last pass (Ns = L / RL): butterfly j = t + i L/8 reads points j + m L/RL
+      if constexpr (RL == 4) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          float2 b0 = a[i], b1 = cmul(a[i + 2], wl[4 * i + 1]), b2 = cmul(a[i + 4], wl[4 * i + 2]),
+                 b3 = cmul(a[i + 6], wl[4 * i + 3]);
+          dft4(b0, b1, b2, b3);
+          a[i] = b0; a[i + 2] = b1; a[i + 4] = b2; a[i + 6] = b3;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float2 b = cmul(a[i + 4], wl[i]);
+          const float2 u = a[i];
+          a[i] = cadd(u, b);
+          a[i + 4] = csub(u, b);
+        }
+      }
+      exchange_write(E0 ^ 1, SwzY{}, a, [&](int m) { return t + m * TH; });
+      ybuf = E0 ^ 1;
+    }
+    __syncthreads();
+    // Eq. 2 split: lane u takes pair u % P of channel u / P (+ r L/8), so
+    // the P pairs of a channel are written by neighbouring lanes
+    float4* o = out + ((int64_t)s * F) * pairs + qg * P;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int u = threadIdx.x;
+      const int p2 = u % P;
+      const int k = u / P + r * TH;
+      const float2 yk = lds_all[ybuf][p2][SwzY{}(k)], ym = lds_all[ybuf][p2][SwzY{}((L - k) & (L - 1))];
+      const float dr = yk.x - ym.x, di = yk.y + ym.y;   // Y[k] - conj(Y[-k])
+      o[(int64_t)k * pairs + p2] = make_float4(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y), 0.5f * di, -0.5f * dr);
+    }
+  };
+
+  for (int s = s0; s < s1; s += 4) {
+    spectrum(std::integral_constant<int, 0>{}, s);
+    if (s + 1 >= s1) break;
+    spectrum(std::integral_constant<int, 1>{}, s + 1);
+    if (s + 2 >= s1) break;
+    spectrum(std::integral_constant<int, 2>{}, s + 2);
+    if (s + 3 >= s1) break;
+    spectrum(std::integral_constant<int, 3>{}, s + 3);
+  }
+}
+
 int log2_exact(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -204,6 +436,28 @@ int channelise_impl(const int8_t* d_adc, int64_t n_samples, int32_t n_inputs, in
   if (S > 0) {
     if (S > 2147483647LL) return XENG_EINVAL;
     const int pairs = n_inputs / 2;
+    if (L >= 512) {
+      // two pairs per workgroup when the pair count allows, runs of
+      // REG_CHUNK spectra
+      const int P = pairs % 2 == 0 ? 2 : 1;
+      const int64_t wgs = (int64_t)(pairs / P) * ((S + xeng::REG_CHUNK - 1) / xeng::REG_CHUNK);
+      if (wgs > 2147483647LL) return XENG_EINVAL;
+      const dim3 grid((unsigned)wgs), block((unsigned)(P * L / 8));
+      auto out4 = reinterpret_cast<float4*>(d_out);
+      const int chunk = xeng::REG_CHUNK;
+#define XENG_CHAN_REG(LL, PP)                                                                                 \
+  hipLaunchKernelGGL((xeng::channelise_reg<LL, PP>), grid, block, 0, st, d_adc, n_samples, n_inputs, (int)S, \
+                     chunk, d_tables, out4)
+      if (L == 512) {
+        if (P == 2) XENG_CHAN_REG(512, 2); else XENG_CHAN_REG(512, 1);
+      } else if (L == 1024) {
+        if (P == 2) XENG_CHAN_REG(1024, 2); else XENG_CHAN_REG(1024, 1);
+      } else {
+        if (P == 2) XENG_CHAN_REG(2048, 2); else XENG_CHAN_REG(2048, 1);
+      }
+#undef XENG_CHAN_REG
+      return hipGetLastError() == hipSuccess ? XENG_OK : XENG_EDEVICE;
+    }
     int G = xeng::G_MAX;
     while (pairs % G) G >>= 1;
     const size_t lds = (size_t)2 * G * L * sizeof(float2);  // up to 128 KB
