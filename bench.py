@@ -54,6 +54,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -87,10 +88,59 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, calls: int = 1):
+TUNE_FILE = os.path.join(ROOT, "paper_1904_07778_amd", "tune_gfx950.txt")
+KIND_NAMES = {0: "16-row ring", 1: "32-row ring", 2: "staging"}
+
+
+def _bucket(v: int) -> int:
+    """ceil(log2 v), the tuning cache's F and T buckets."""
+    b = 0
+    while (1 << b) < v and b < 62:
+        b += 1
+    return b
+
+
+def tuned_choices(shapes, batched: bool) -> str:
+    """The launch choices the library holds for these arrays, as text (from
+    a save of the in-process tuning cache)."""
+    from paper_1904_07778_amd import xeng as X
+    fd, path = tempfile.mkstemp(suffix=".txt")
+    os.close(fd)
+    try:
+        X.xeng_tune_cache_save(path)
+        table = {}
+        with open(path) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 8 and not line.startswith("#"):
+                    table[(int(f[1]), int(f[2]), int(f[3]), int(f[4]))] = (int(f[5]), int(f[6]), int(f[7]))
+    finally:
+        os.unlink(path)
+    out = []
+    for n, f, t in shapes:
+        c = table.get((int(batched), n, _bucket(f), _bucket(t)))
+        out.append("untuned" if c is None else
+                   f"N={n}: {KIND_NAMES.get(c[0], c[0])} split {c[1]}{' own launch' if c[2] else ''}")
+    return "; ".join(out)
+
+
+def load_tuning(args) -> str | None:
+    """Load the tuning cache (--tune-cache, else the library's shipped
+    file) into the library; returns the path loaded, or None."""
+    from paper_1904_07778_amd import xeng as X
+    path = args.tune_cache or TUNE_FILE
+    if os.path.exists(path):
+        X.xeng_tune_cache_load(path)
+        log(f"tuning cache loaded from {path}")
+        return path
+    return None
+
+
+def measured_traffic(workload: str, tuned: str):
     """HBM bytes per step from the committed rocprofv3 counter summary of this
     workload (profiles/xcorr_<workload>_counters.txt), or None when it is
-    missing, was taken on another workload or on different kernel sources."""
+    missing, was taken on another workload, on different kernel sources or
+    with other launch choices."""
     path = os.path.join(PROFILES, f"xcorr_{workload}_counters.txt")
     try:
         with open(path) as fh:
@@ -98,7 +148,8 @@ def measured_traffic(workload: str, calls: int = 1):
     except OSError:
         return None
     rec = {k.strip(): v.strip() for k, v in rec.items()}
-    if rec.get("workload") != workload or rec.get("kernel_source_sha1") != kernel_source_hash():
+    if (rec.get("workload") != workload or rec.get("kernel_source_sha1") != kernel_source_hash()
+            or rec.get("tuned") != tuned):
         return None
     try:
         return float(rec["hbm_bytes_per_step"])
@@ -151,8 +202,12 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--settle-seconds", type=float, default=1.0,
                     help="untimed run of the step before the warm-up (plain workloads)")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune even where the tuning cache has a choice, and save the cache "
+                         "(to --tune-cache, else the library's shipped file)")
     ap.add_argument("--tune-cache", default=None,
-                    help="batch: load the autotuner's choices from this file if it exists, else tune and save")
+                    help="tuning cache to load (default: the library's shipped file); arrays it has no "
+                         "choice for are autotuned")
     ap.add_argument("--batched-only", action="store_true",
                     help="batch: run warm-up + steps batched calls only (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -234,12 +289,20 @@ def bench_plain(args) -> int:
     log(f"generated in {time.perf_counter() - t0:.1f} s")
     v = [torch.from_numpy(h).cuda() for h in v_host]
 
+    from paper_1904_07778_amd import xeng as X
+    load_tuning(args)
     stream = torch.cuda.current_stream()
     plan = Plan([(N, F, T)], stream=stream)
     out = plan.new_output(0)
     torch.cuda.synchronize()
-    tuned_ms = plan.autotune([v[0]], reps=3)
-    log(f"autotuned: {tuned_ms:.4f} ms per call")
+    tuned_ms = None
+    if args.retune or "untuned" in tuned_choices([(N, F, T)], False):
+        tuned_ms = plan.autotune([v[0]], reps=3)
+        log(f"autotuned: {tuned_ms:.4f} ms per call")
+        if args.retune:
+            X.xeng_tune_cache_save(args.tune_cache or TUNE_FILE)
+    tuned = tuned_choices([(N, F, T)], False)
+    log(f"launch choice: {tuned} ({'autotuned' if tuned_ms is not None else 'tuning cache'})")
 
     def step(events=None):
         for k in range(calls):
@@ -313,7 +376,7 @@ def bench_plain(args) -> int:
         achieved = cmac_per_step * OPS_PER_CMAC / (dev_mean / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
                 "frac": achieved / PEAK_INT8_TOPS}
-    roof.update({"traffic": measured_traffic(name, calls), "algorithmic_bytes": alg_bytes,
+    roof.update({"traffic": measured_traffic(name, tuned), "algorithmic_bytes": alg_bytes,
                  "hbm_gbs_algorithmic": alg_bytes / (dev_mean / 1e3) / 1e9,
                  "int8_tops": cmac_per_step * OPS_PER_CMAC / (dev_mean / 1e3) / 1e12,
                  "time": "device time of the K timed steps (one HIP event pair on the engine stream) / K"})
@@ -342,7 +405,9 @@ def bench_plain(args) -> int:
                    "n_inputs": N, "n_chans": F, "n_time": T, "calls_per_integration": calls,
                    "step": ("correlate + dump in one call (xeng_correlate_dump)" if calls == 1 else
                             f"{calls - 1} xeng_correlate calls, then xeng_correlate_dump"),
-                   "settle_s": args.settle_seconds, "autotuned_ms_per_call": tuned_ms},
+                   "settle_s": args.settle_seconds, "launch": tuned,
+                   "launch_from": "autotune" if tuned_ms is not None else "tuning cache",
+                   "autotuned_ms_per_call": tuned_ms},
         "kernel_ms": dev_mean,
         "step_event_ms": {"median": float(np.median(step_dev_ms)), "min": float(step_dev_ms.min()),
                           "mean": float(step_dev_ms.mean()), "max": float(step_dev_ms.max()),
@@ -385,21 +450,22 @@ def bench_batch(args) -> int:
     out_bytes = sum(n * (n + 1) // 2 * f * 8 for n, f, t in shapes)
     from paper_1904_07778_amd import xeng as X
     stream = torch.cuda.current_stream()
-    cached = bool(args.tune_cache) and os.path.exists(args.tune_cache)
-    if cached:
-        X.xeng_tune_cache_load(args.tune_cache)          # plans start from the cached choices
-        log(f"tuning cache loaded from {args.tune_cache}")
+    load_tuning(args)                                    # plans start from the cached choices
     batched = Plan(shapes, stream=stream)
     plain = [Plan([sh], stream=stream) for sh in shapes]
     torch.cuda.synchronize()
     tb = tp = None
+    cached = not (args.retune or "untuned" in tuned_choices(shapes, True)
+                  or "untuned" in tuned_choices(shapes, False))
     if not cached:
         log("autotuning")
         tb = batched.autotune(dev, reps=3)
         tp = sum(p.autotune([v], reps=3) for p, v in zip(plain, dev))
         log(f"autotuned: batched {tb:.3f} ms, plain sum {tp:.3f} ms")
-        if args.tune_cache:
-            X.xeng_tune_cache_save(args.tune_cache)
+        if args.retune:
+            X.xeng_tune_cache_save(args.tune_cache or TUNE_FILE)
+    tuned = tuned_choices(shapes, True)
+    log(f"batched launch choices: {tuned}")
     out_b = [batched.new_output(k) for k in range(len(shapes))]
     out_p = [p.new_output(0) for p in plain]
     if args.batched_only:      # counter runs: the batched steps alone
@@ -439,7 +505,8 @@ def bench_batch(args) -> int:
                        {"workload": "batch: 12 arrays, N in {16..192}, F in {256, 512, 1024}, "
                                     "T in {2048, 4096, 8192} (seed 4), 4+4-bit complex",
                         "arrays": shapes,
-                        "step": "batched correlate + dump of all arrays in one call (xeng_correlate_dump)"})
+                        "step": "batched correlate + dump of all arrays in one call (xeng_correlate_dump)",
+                        "launch": tuned, "launch_from": "tuning cache" if cached else "autotune"})
     # the mix's combined bound: its bytes at 8 TB/s or its int8 work at 5 POP/s
     t_hbm = (in_bytes + out_bytes) / (PEAK_HBM_GBS * 1e9)
     t_mfma = cmac * OPS_PER_CMAC / (PEAK_INT8_TOPS * 1e12)
@@ -456,7 +523,7 @@ def bench_batch(args) -> int:
         "int8_mfma_frac_of_step": cmac * OPS_PER_CMAC / (ms_b / 1e3) / (PEAK_INT8_TOPS * 1e12),
         "roofline": {"bound": "hbm" if hbm_dom else "mfma", "achieved": achieved, "peak": peak,
                      "unit": "GB/s" if hbm_dom else "TOP/s", "frac": achieved / peak,
-                     "traffic": measured_traffic("batch"), "algorithmic_bytes": in_bytes + out_bytes,
+                     "traffic": measured_traffic("batch", tuned), "algorithmic_bytes": in_bytes + out_bytes,
                      "combined_bound_ms": max(t_hbm, t_mfma) * 1e3,
                      "note": "whole step (the graph: batch kernel, any own launches, carry-over copies) "
                              "on the engine stream, against the mix's bytes at 8 TB/s or its int8 work "
