@@ -79,10 +79,14 @@ KERNEL_SOURCES = ("xcorr.hpp", "xcorr16.hpp", "xcorr32.hpp", "k_x16_a.hip", "k_x
                   "batch.hpp", "k_batch.hip", "k_dump.hip", "xeng.hip")
 
 
-def kernel_source_hash() -> str:
-    """Hash of the timed kernel's source files."""
+# sources of the F-stage kernels, per bench workload
+FSTAGE_SOURCES = {"chan": ("k_chan.hip",), "requant": ("k_requant.hip",), "ingest": ("k_ingest.hip",)}
+
+
+def kernel_source_hash(names=KERNEL_SOURCES) -> str:
+    """Hash of the timed kernels' source files."""
     h = hashlib.sha1()
-    for name in KERNEL_SOURCES:
+    for name in names:
         with open(os.path.join(CSRC, name), "rb") as fh:
             h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -136,20 +140,20 @@ def load_tuning(args) -> str | None:
     return None
 
 
-def measured_traffic(workload: str, tuned: str):
+def measured_traffic(workload: str, tuned: str | None, prefix: str = "xcorr", sources=KERNEL_SOURCES):
     """HBM bytes per step from the committed rocprofv3 counter summary of this
-    workload (profiles/xcorr_<workload>_counters.txt), or None when it is
+    workload (profiles/<prefix>_<workload>_counters.txt), or None when it is
     missing, was taken on another workload, on different kernel sources or
     with other launch choices."""
-    path = os.path.join(PROFILES, f"xcorr_{workload}_counters.txt")
+    path = os.path.join(PROFILES, f"{prefix}_{workload}_counters.txt")
     try:
         with open(path) as fh:
             rec = dict(l.split(":", 1) for l in fh if ":" in l and not l.startswith("#"))
     except OSError:
         return None
     rec = {k.strip(): v.strip() for k, v in rec.items()}
-    if (rec.get("workload") != workload or rec.get("kernel_source_sha1") != kernel_source_hash()
-            or rec.get("tuned") != tuned):
+    if (rec.get("workload") != workload or rec.get("kernel_source_sha1") != kernel_source_hash(sources)
+            or (tuned is not None and rec.get("tuned") != tuned)):
         return None
     try:
         return float(rec["hbm_bytes_per_step"])
@@ -711,7 +715,8 @@ def bench_chan(args) -> int:
     rec.update({"unit": "samples/s", "dtype": "f32", "kernel_ms": kms,
                 "roofline": {"bound": "hbm", "achieved": nbytes / (kms / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
                              "unit": "GB/s", "frac": nbytes / (kms / 1e3) / 1e9 / PEAK_HBM_GBS,
-                             "traffic": None, "algorithmic_bytes": nbytes,
+                             "traffic": measured_traffic("chan", None, "fstage", FSTAGE_SOURCES["chan"]),
+                             "algorithmic_bytes": nbytes,
                              "fp32_tflops": flops / (kms / 1e3) / 1e12},
                 "cpu_baseline": None})
     print(json.dumps(rec), flush=True)
@@ -762,7 +767,8 @@ def bench_ingest(args) -> int:
     rec.update({"unit": "B/s", "dtype": "u8", "kernel_ms": kms,
                 "roofline": {"bound": "hbm", "achieved": nbytes / (kms / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
                              "unit": "GB/s", "frac": nbytes / (kms / 1e3) / 1e9 / PEAK_HBM_GBS,
-                             "traffic": None, "algorithmic_bytes": nbytes},
+                             "traffic": measured_traffic("ingest", None, "fstage", FSTAGE_SOURCES["ingest"]),
+                             "algorithmic_bytes": nbytes},
                 "cpu_baseline": None})
     print(json.dumps(rec), flush=True)
     return 0
@@ -822,7 +828,8 @@ def bench_requant(args) -> int:
     rec.update({"unit": "samples/s", "dtype": "int32", "kernel_ms": kms,
                 "roofline": {"bound": "hbm", "achieved": nbytes / (kms / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
                              "unit": "GB/s", "frac": nbytes / (kms / 1e3) / 1e9 / PEAK_HBM_GBS,
-                             "traffic": None, "algorithmic_bytes": nbytes},
+                             "traffic": measured_traffic("requant", None, "fstage", FSTAGE_SOURCES["requant"]),
+                             "algorithmic_bytes": nbytes},
                 "cpu_baseline": cpu})
     print(json.dumps(rec), flush=True)
     return 0
