@@ -47,8 +47,11 @@ __global__ __launch_bounds__(256) void index_packets(const uint8_t* __restrict__
 }
 
 // One workgroup per time block writes its 8 x C output rows of N bytes in
-// consecutive 8-byte words (fully coalesced stores); word (b, w) of a row
-// comes from board b's packet.
+// 8-byte words; word (b, w) of a row comes from board b's packet.  With a
+// multiple of four boards, the words go in tiles of 4 rows x 4 boards x 4
+// words per wave: each wave then reads one whole 128-byte line of each of
+// four packets (4 consecutive rows of 32 bytes) and writes 128 contiguous
+// bytes of each of the 4 rows.
 __global__ __launch_bounds__(256) void scatter(const uint8_t* __restrict__ pk, int64_t stride,
                                                const int32_t* __restrict__ idx, int n_boards, int n_chans,
                                                uint8_t* __restrict__ out) {
@@ -62,11 +65,23 @@ __global__ __launch_bounds__(256) void scatter(const uint8_t* __restrict__ pk, i
   const int row_words = n_boards * 4;                      // N / 8
   const int words = TIMES * n_chans * row_words;
   uint64_t* dst = reinterpret_cast<uint64_t*>(out) + m * words;
-  for (int q = threadIdx.x; q < words; q += 256) {
-    const int row = q / row_words, wr = q % row_words;     // row = t * C + ch
-    const int b = wr >> 2, w = wr & 3;
-    const uint64_t* s = src[b];
-    dst[q] = s ? __builtin_nontemporal_load(s + 4 * row + w) : 0ull;
+  if (n_boards % 4 == 0) {
+    // q -> (4-row group, 4-board group, row, board, word), word fastest
+    const int groups = n_boards / 4;
+    for (int q = threadIdx.x; q < words; q += 256) {
+      const int j = q & 63, tile = q >> 6;
+      const int row = (tile / groups) * 4 + (j >> 4);      // rows 8C is a multiple of 4
+      const int b = (tile % groups) * 4 + ((j >> 2) & 3), w = j & 3;
+      const uint64_t* s = src[b];
+      dst[(int64_t)row * row_words + b * 4 + w] = s ? s[4 * row + w] : 0ull;
+    }
+  } else {
+    for (int q = threadIdx.x; q < words; q += 256) {
+      const int row = q / row_words, wr = q % row_words;   // row = t * C + ch
+      const int b = wr >> 2, w = wr & 3;
+      const uint64_t* s = src[b];
+      dst[q] = s ? s[4 * row + w] : 0ull;
+    }
   }
 }
 

@@ -27,7 +27,8 @@ def messy_buffer(rng, blk, mcnt0, xid, stride=None):
 
 
 @pytest.mark.parametrize("blocks,boards,chans,stride", [(4, 1, 32, None), (9, 6, 32, None), (5, 8, 16, None),
-                                                        (3, 2, 32, 8216), (1, 3, 5, None)])
+                                                        (3, 2, 32, 8216), (1, 3, 5, None),
+                                                        (2, 4, 7, None), (3, 8, 5, 8216)])
 def test_messy_packets_match_oracle(blocks, boards, chans, stride):
     import torch
     from paper_1904_07778_amd.xeng import ingest
