@@ -193,6 +193,32 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5) -> None:
     print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
 
 
+def hbm_probe(nbytes: int = 4 << 30, reps: int = 10) -> None:
+    """Reachable HBM bandwidth on this GPU, for context beside the 8 TB/s peak:
+    a device-to-device copy (read + write, 1:1) and a read-dominated
+    reduction, each timed with HIP events over `reps` calls."""
+    import torch
+    x = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").fill_(1)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+
+    def rate(fn, moved):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+    copy = rate(lambda: y.copy_(x), 2 * nbytes)
+    read = rate(lambda: torch.sum(x), nbytes)
+    print(json.dumps({"hbm_probe": {"copy_read_plus_write_gbs": copy, "sum_read_gbs": read,
+                                    "bytes": nbytes, "reps": reps, "peak_gbs": PEAK_HBM_GBS}}))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +242,8 @@ def main() -> int:
                     help="batch: run warm-up + steps batched calls only (for counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="print the copy and read bandwidth this GPU reaches, then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -239,6 +267,9 @@ def main() -> int:
     torch.cuda.set_stream(torch.cuda.Stream())
     if args.copy_calibration:
         copy_calibration()
+        return 0
+    if args.hbm_probe:
+        hbm_probe()
         return 0
 
     if args.workload == "batch":
