@@ -125,6 +125,9 @@ def tuned_choices(shapes, batched: bool) -> str:
         c = table.get((int(batched), n, _bucket(f), _bucket(t)))
         out.append("untuned" if c is None else
                    f"N={n}: {KIND_NAMES.get(c[0], c[0])} split {c[1]}{' own launch' if c[2] else ''}")
+    plan = table.get((1, 0, 0, _bucket(len(shapes)))) if batched else None
+    if plan is not None:
+        out.append(f"persistent launch: {plan[1]} items per workgroup")
     return "; ".join(out)
 
 

@@ -234,7 +234,9 @@ int xeng_autotune(xeng_plan_t *p, const uint8_t *const *d_voltages, const int64_
  * xeng_tune_cache_save / xeng_tune_cache_load / xeng_tune_cache_clear - the
  * process-wide tuning cache of xeng_autotune as a text file (one choice per
  * line: architecture, batched, N, log2 F bucket, log2 T bucket, tile shape,
- * time split, own launch), so a later process skips the timing.  Loading
+ * time split, own launch; a batched plan's items per workgroup are kept as a
+ * line with N = 0, F bucket 0 and the log2 bucket of its array count in
+ * place of the T bucket), so a later process skips the timing.  Loading
  * adds to (and overrides) what the cache holds; plans made afterwards use
  * it.  Errors: EINVAL (null path, file not readable or writable; for load
  * also malformed lines, which are skipped).

@@ -188,6 +188,16 @@ void apply_cached(const xeng_plan_t* p, ArrayState& s, int64_t T) {
   s.own_launch = p->batched && it->second.own;
 }
 
+// The batched plan's own choice (items per workgroup) is kept under N = 0,
+// keyed by the base-2 bucket of the plan's array count.
+TuneKey plan_key(const xeng_plan_t* p, int32_t n_arrays) { return TuneKey{p->arch, 1, 0, 0, bucket(n_arrays)}; }
+
+void apply_cached_plan(xeng_plan_t* p, int32_t n_arrays) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(plan_key(p, n_arrays));
+  if (it != g_tune.end()) p->batch_split = it->second.split;
+}
+
 void record_choice(const xeng_plan_t* p, const ArrayState& s, int64_t T) {
   const TuneKey key{p->arch, p->batched ? 1 : 0, s.d.n_inputs, bucket(s.d.n_chans), bucket(T)};
   std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -573,6 +583,7 @@ int xeng_plan(xeng_plan_t** out, const xeng_array_desc* arrays, int32_t n_arrays
       return st;
     }
   }
+  if (p->batched) apply_cached_plan(p, n_arrays);
   *out = p;
   return XENG_OK;
 }
@@ -791,6 +802,10 @@ int xeng_autotune(xeng_plan_t* p, const uint8_t* const* d_voltages, const int64_
       }
     }
     for (int32_t a : order) record_choice(p, p->arrays[a], n_time[a]);
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tune[plan_key(p, (int32_t)p->arrays.size())] = TuneVal{KIND_X16, p->batch_split, 0};
+    }
   } else {
     // per array: tile shape (32-row tiles of the ring kernel or 16-row tiles
     // of the staging kernel) and workgroups per CU of the time split
@@ -863,7 +878,8 @@ int xeng_tune_cache_load(const char* path) {
     char arch[128];
     int b, n, fb, tb, kind, split, own;
     if (sscanf(line, "%127s %d %d %d %d %d %d %d", arch, &b, &n, &fb, &tb, &kind, &split, &own) != 8 ||
-        n < 1 || n > XENG_MAX_INPUTS || kind < KIND_X16 || kind > KIND_STAGE || split < 1 || split > 64) {
+        n < 0 || n > XENG_MAX_INPUTS || (n == 0 && !b) || kind < KIND_X16 || kind > KIND_STAGE || split < 1 ||
+        split > 64) {
       st = XENG_EINVAL;  // malformed line: skipped, reported
       continue;
     }

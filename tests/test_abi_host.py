@@ -151,6 +151,8 @@ def test_tune_cache_file_round_trip(tmp_path):
     src.write_text("# comment\n"
                    "gfx950 0 192 10 13 0 2 0\n"
                    "gfx950 1 32 10 11 1 1 1\n"
+                   "gfx950 1 0 0 4 0 4 0\n"        # a batched plan's items per workgroup
+                   "gfx950 0 0 0 4 0 4 0\n"        # N = 0 is for batched plans only
                    "gfx950 0 999 10 13 0 2 0\n"     # N out of range
                    "garbage line\n")
     with pytest.raises(X.XengError) as ei:
@@ -159,7 +161,7 @@ def test_tune_cache_file_round_trip(tmp_path):
     out = tmp_path / "saved.txt"
     X.xeng_tune_cache_save(str(out))
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
-    assert sorted(lines) == ["gfx950 0 192 10 13 0 2 0", "gfx950 1 32 10 11 1 1 1"]
+    assert sorted(lines) == ["gfx950 0 192 10 13 0 2 0", "gfx950 1 0 0 4 0 4 0", "gfx950 1 32 10 11 1 1 1"]
     X.xeng_tune_cache_clear()
     X.xeng_tune_cache_save(str(out))
     assert [l for l in out.read_text().splitlines() if not l.startswith("#")] == []

@@ -286,7 +286,8 @@ def test_cached_own_launches_in_a_batched_plan(tmp_path):
     lines = [f"{dev_arch} 1 192 {bucket(3)} {bucket(700)} 0 1 1",     # own launch, 16-row tiles
              f"{dev_arch} 1 48 {bucket(5)} {bucket(1500)} 1 2 1",     # own launch, 32-row tiles
              f"{dev_arch} 1 32 {bucket(4)} {bucket(300)} 2 1 1",      # own launch, staging kernel
-             f"{dev_arch} 0 64 {bucket(2)} {bucket(1000)} 1 4 0"]     # plain plan: 32-row tiles
+             f"{dev_arch} 0 64 {bucket(2)} {bucket(1000)} 1 4 0",     # plain plan: 32-row tiles
+             f"{dev_arch} 1 0 0 {bucket(4)} 0 8 0"]                   # batched plan: 8 items per workgroup
     f = tmp_path / "tune.txt"
     f.write_text("\n".join(lines) + "\n")
     X.xeng_tune_cache_clear()
