@@ -93,6 +93,7 @@ def kernel_source_hash(names=KERNEL_SOURCES) -> str:
 
 
 TUNE_FILE = os.path.join(ROOT, "paper_1904_07778_amd", "tune_gfx950.txt")
+TUNE_REPS = 10   # timed calls per autotuner trial
 KIND_NAMES = {0: "16-row ring", 1: "32-row ring", 2: "staging"}
 
 
@@ -335,7 +336,12 @@ def bench_plain(args) -> int:
     torch.cuda.synchronize()
     tuned_ms = None
     if args.retune or "untuned" in tuned_choices([(N, F, T)], False):
-        tuned_ms = plan.autotune([v[0]], reps=3)
+        t_settle = time.perf_counter()
+        while time.perf_counter() - t_settle < args.settle_seconds:
+            for _ in range(8):
+                plan.correlate_dump([v[0]], out=[out])
+            torch.cuda.synchronize()
+        tuned_ms = plan.autotune([v[0]], reps=TUNE_REPS)
         log(f"autotuned: {tuned_ms:.4f} ms per call")
         if args.retune:
             X.xeng_tune_cache_save(args.tune_cache or TUNE_FILE)
@@ -496,9 +502,18 @@ def bench_batch(args) -> int:
     cached = not (args.retune or "untuned" in tuned_choices(shapes, True)
                   or "untuned" in tuned_choices(shapes, False))
     if not cached:
+        # the shader clock settles before the trials, and each trial times
+        # enough calls that run-to-run noise does not decide the pick
+        out_b0 = [batched.new_output(k) for k in range(len(shapes))]
+        t_settle = time.perf_counter()
+        while time.perf_counter() - t_settle < args.settle_seconds:
+            for _ in range(8):
+                batched.correlate_dump(dev, out=out_b0)
+            torch.cuda.synchronize()
+        del out_b0
         log("autotuning")
-        tb = batched.autotune(dev, reps=3)
-        tp = sum(p.autotune([v], reps=3) for p, v in zip(plain, dev))
+        tb = batched.autotune(dev, reps=TUNE_REPS)
+        tp = sum(p.autotune([v], reps=TUNE_REPS) for p, v in zip(plain, dev))
         log(f"autotuned: batched {tb:.3f} ms, plain sum {tp:.3f} ms")
         if args.retune:
             X.xeng_tune_cache_save(args.tune_cache or TUNE_FILE)
