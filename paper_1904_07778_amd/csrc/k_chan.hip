@@ -1,17 +1,19 @@
 // k_chan.hip - F-stage channeliser (paper Sec. 2.1, Eq. 1-2) and its C
 // entry points (include/xeng.h).
 //
-// Per spectrum s and input pair (2q, 2q + 1) (G pairs per workgroup):
+// Per spectrum s and input pair (2q, 2q + 1):
 //  1. polyphase FIR: v[n] = sum_{p<4} h[pL + n] x[sL + pL + n] for both
 //     inputs (L = 2F real samples per spectrum, h the Hamming-windowed sinc
-//     prototype), packed as y[n] = v_2q[n] + j v_2q+1[n] (Eq. 1) in LDS;
-//  2. Stockham FFT of y, L points (radix 4, and one radix-2 step when
-//     log2 L is odd), natural order out;
+//     prototype), packed as y[n] = v_2q[n] + j v_2q+1[n] (Eq. 1);
+//  2. Stockham FFT of y, L points, natural order out;
 //  3. Eq. 2: X_2q[k] = (Y[k] + conj Y[-k]) / 2, X_2q+1[k] = (Y[k] -
 //     conj Y[-k]) / 2j, k < F, written to out[s][k][2q .. 2q + 1] (the
 //     [time, channel, input] order of the X side).
-// Float32 arithmetic; the tables (h and the twiddles e^{-2 pi i t / L}) are
-// computed in double and rounded once.
+// Two kernels: for F = 256, 512, 1024 a register-resident one (radix-8
+// passes, runs of spectra per workgroup, below); for other F one workgroup
+// per (spectrum, pair) with the points in LDS (radix-4 passes and one
+// radix-2 pass when log2 L is odd).  Float32 arithmetic; the tables (h and
+// the twiddles e^{-2 pi i t / L}) are computed in double and rounded once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
