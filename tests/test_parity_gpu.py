@@ -44,7 +44,8 @@ SWEEP = [(1, 1, 1), (2, 3, 31), (3, 5, 33), (5, 2, 100), (8, 7, 64), (15, 3, 257
          (96, 3, 1024), (100, 2, 77), (112, 2, 300), (127, 1, 513), (128, 3, 1000),
          (144, 2, 256), (150, 1, 99), (160, 2, 640), (176, 2, 160), (191, 1, 400),
          (192, 3, 512), (200, 2, 200), (224, 1, 96), (240, 1, 1100), (255, 1, 65),
-         (256, 2, 384), (1, 1, 100000), (48, 1, 70000), (192, 1, 20000)]
+         (256, 2, 384), (1, 1, 100000), (48, 1, 70000), (192, 1, 20000),
+         (208, 3, 777), (160, 5, 321), (128, 7, 4097), (240, 2, 65), (16, 9, 33000)]
 
 
 @pytest.mark.parametrize("N,F,T", SWEEP, ids=lambda x: str(x))
