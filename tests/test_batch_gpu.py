@@ -227,6 +227,43 @@ def test_full_batched_workload_all_channels():
         assert np.array_equal(got, want), f"array {k}: " + first_mismatch(got, want)
 
 
+def test_full_batched_workload_shipped_launch_choices():
+    """The 12-array workload in the launch the benchmark runs by default: the
+    tuning cache shipped with the library, loaded before the plans are made.
+    Batched and plain outputs equal the oracle on every channel."""
+    import os
+    import torch
+    from paper_1904_07778_amd import xeng as X
+    from paper_1904_07778_amd.xeng import Plan
+    path = os.path.join(os.path.dirname(X.__file__), "tune_gfx950.txt")
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    if arch != "gfx950" or not os.path.exists(path):
+        pytest.skip("the shipped launch choices are for gfx950")
+    specs = synth.batch_arrays()
+    print("full batched workload, shipped launch choices", flush=True)
+    host = [synth.voltages("noise", 4, s["n_inputs"], s["n_chans"], s["n_time"], array=k)
+            for k, s in enumerate(specs)]
+    dev = [to_dev(h) for h in host]
+    shapes = [(s["n_inputs"], s["n_chans"], s["n_time"]) for s in specs]
+    X.xeng_tune_cache_clear()
+    X.xeng_tune_cache_load(path)
+    try:
+        with Plan(shapes) as p:
+            batched, _ = p.correlate_dump(dev)
+        plain = []
+        for sh, v in zip(shapes, dev):
+            with Plan([sh]) as q:
+                plain.append(q.correlate_dump([v])[0][0])
+    finally:
+        X.xeng_tune_cache_clear()
+    torch.cuda.synchronize()
+    for k, (s, h) in enumerate(zip(specs, host)):
+        want = oracle_vis([h], s["n_inputs"], s["n_chans"])
+        got = batched[k].cpu().numpy()
+        assert np.array_equal(got, want), f"array {k}: " + first_mismatch(got, want)
+        assert torch.equal(plain[k], batched[k]), f"array {k}: plain != batched"
+
+
 def test_batched_restart_after_dump_with_time_split():
     """Batched call whose items split time (atomic adds) right after a dump
     that left the old sums in memory."""
