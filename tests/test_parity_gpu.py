@@ -177,6 +177,42 @@ def test_dish_scale_eight_calls_all_channels():
     assert (autos[..., 1] == 0).all() and (autos[..., 0] >= 0).all()
 
 
+@pytest.mark.parametrize("name", ["dish_tiny", "dish", "cylinder"])
+def test_full_workload_in_shipped_launch_choices(name):
+    """Each plain workload at full size in the launch the benchmark runs by
+    default (the tuning cache shipped with the library), integrated over its
+    calls with correlate and finished with correlate_dump as the bench step
+    does: every channel against the oracle."""
+    import os
+    import torch
+    from paper_1904_07778_amd import xeng as X
+    from paper_1904_07778_amd.xeng import Plan
+    path = os.path.join(os.path.dirname(X.__file__), "tune_gfx950.txt")
+    if torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] != "gfx950" or not os.path.exists(path):
+        pytest.skip("the shipped launch choices are for gfx950")
+    w = synth.WORKLOADS[name]
+    N, F, T, calls = w["n_inputs"], w["n_chans"], w["n_time"], w["calls"]
+    print(f"{name} in shipped launch choices: N={N} F={F} T={T} x {calls}", flush=True)
+    blocks = [synth.voltages(w["recipe"], w["seed"], N, F, T, block=b) if calls > 1 else
+              synth.voltages(w["recipe"], w["seed"], N, F, T) for b in range(calls)]
+    X.xeng_tune_cache_clear()
+    X.xeng_tune_cache_load(path)
+    try:
+        with Plan([(N, F, T)]) as p:
+            for b in blocks[:-1]:
+                p.correlate([torch.from_numpy(b).cuda()])
+            out, n = p.correlate_dump([torch.from_numpy(blocks[-1]).cuda()])
+            got = out[0].cpu().numpy()
+    finally:
+        X.xeng_tune_cache_clear()
+    assert n[0] == T * calls
+    e = oracle.Engine(N, F)
+    for b in blocks:
+        e.correlate(b)
+    want, _ = e.dump()
+    assert np.array_equal(got, want), first_mismatch(got, want)
+
+
 def test_cylinder_scale_all_channels():
     """Cylinder workload at full size in the launch the benchmark times (one
     fused correlate-and-dump call into a device buffer): every channel
