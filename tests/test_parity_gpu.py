@@ -148,21 +148,29 @@ def test_caller_on_the_engine_stream():
     assert np.array_equal(got0, want0), first_mismatch(got0, want0)
 
 
-def test_integration_exact_at_int32_bound():
-    """One input, all codes -8: the auto reaches 128 * 16,777,215 = 2,147,483,520,
-    the largest integration the library accepts, and must be exact."""
+@pytest.mark.parametrize("N", [1, 40])
+def test_integration_exact_at_int32_bound(N):
+    """Staging kernel (N not a multiple of 16; N = 40 spans three 16-row
+    tiles), all codes -8: every visibility reaches 128 * 16,777,215 =
+    2,147,483,520, the largest integration the library accepts, and must be
+    exact; one sample more is refused."""
     import torch
     from paper_1904_07778_amd.xeng import XENG_EOVERFLOW, XENG_MAX_INTEGRATION, Plan, XengError
     T = XENG_MAX_INTEGRATION
-    v = torch.full((T, 1, 1), 0x88, dtype=torch.uint8, device="cuda")
-    with Plan([(1, 1, T)]) as p:
+    print(f"staging kernel int32 bound N={N}", flush=True)
+    v = torch.full((T, 1, N), 0x88, dtype=torch.uint8, device="cuda")
+    with Plan([(N, 1, T)]) as p:
         p.correlate([v])
         with pytest.raises(XengError) as ei:
             p.correlate([v[:1]])
         assert ei.value.status == XENG_EOVERFLOW
         out, n = p.dump(to_host=True)
+    del v
     assert n == [T]
-    assert out[0].numpy().tolist() == [[[128 * T, 0]]]
+    got = out[0].numpy()
+    want = np.broadcast_to(np.array([128 * T, 0], np.int32), got.shape)
+    assert got.shape == (1, N * (N + 1) // 2, 2)
+    assert np.array_equal(got, want), first_mismatch(got, want)
 
 
 def test_dish_scale_eight_calls_all_channels():
@@ -249,13 +257,16 @@ def _closed_form(re, im, T):
 
 
 @pytest.mark.parametrize("batched", [False, True], ids=["plain", "batched"])
-@pytest.mark.parametrize("N", [16, 192])
+@pytest.mark.parametrize("N", [16, 192, 256])
 def test_ring_kernel_at_int32_bound(N, batched):
-    """32-row-tile ring kernel at the library's integration limit: all codes
-    -8, T = 16,777,215 in one call, so every workgroup integrates the largest
-    time chunk the kernel takes (its x256-scaled sums at their headroom) and
-    the chunks meet in the accumulator by atomic adds.  Every visibility must
-    be 128 T = 2,147,483,520 (the closed form), exact."""
+    """Ring kernels at the library's integration limit: all codes -8,
+    T = 16,777,215 in one call, so every workgroup integrates the largest
+    time chunk its kernel takes (the x256-scaled sums at their headroom) and
+    the chunks meet in the accumulator by atomic adds.  N = 16 and 192 run
+    the 16-row-tile kernel (in a batched plan, inside the persistent launch);
+    N = 256 the 32-row-tile kernel (in a batched plan, as a launch of its
+    own).  Every visibility must be 128 T = 2,147,483,520 (the closed form),
+    exact."""
     import torch
     from paper_1904_07778_amd.xeng import XENG_MAX_INTEGRATION, Plan
     T, F = XENG_MAX_INTEGRATION, 1
