@@ -32,9 +32,11 @@ def test_loss_duplicates_and_foreign_packets():
     keep = [p for p in range(len(pk)) if p != 3]              # (mcnt 51, board 1) lost
     foreign = synth.packets(rng.integers(0, 256, size=(8, 32, 64), dtype=np.uint8), 50, xid=2)
     late = synth.packets(rng.integers(0, 256, size=(8, 32, 64), dtype=np.uint8), 60, xid=1)
+    # the first time block past the block assembled (MCNT 54) is ignored too
+    edge = synth.packets(rng.integers(0, 256, size=(8, 32, 64), dtype=np.uint8), 54, xid=1)
     dup = pk[[0]].copy()
     dup[0, 8:] = 0xAB                                          # a later copy of (50, board 0)
-    buf = np.concatenate([pk[keep], foreign, late, dup])
+    buf = np.concatenate([pk[keep], foreign, late, edge, dup])
     out, idx = I.assemble(buf, 50, 4, 2, 32, 1)
     want = blk.copy()
     want[8:16, :, 32:64] = 0                                   # the lost packet reads as zeros
