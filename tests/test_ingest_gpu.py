@@ -23,7 +23,10 @@ def messy_buffer(rng, blk, mcnt0, xid, stride=None):
     dup[:, 8:] = rng.integers(0, 256, size=dup[:, 8:].shape, dtype=np.uint8)
     junk = synth.packets(rng.integers(0, 256, size=(16,) + blk.shape[1:], dtype=np.uint8), mcnt0, xid + 1, stride)
     stale = synth.packets(rng.integers(0, 256, size=(16,) + blk.shape[1:], dtype=np.uint8), mcnt0 - 2, xid, stride)
-    return np.concatenate([pk[keep], junk, dup, stale, pk[keep[:2]]])
+    # the two time blocks right after the block assembled (ignored)
+    past = synth.packets(rng.integers(0, 256, size=(16,) + blk.shape[1:], dtype=np.uint8),
+                         mcnt0 + blk.shape[0] // 8, xid, stride)
+    return np.concatenate([pk[keep], junk, dup, stale, past, pk[keep[:2]]])
 
 
 @pytest.mark.parametrize("blocks,boards,chans,stride", [(4, 1, 32, None), (9, 6, 32, None), (5, 8, 16, None),
