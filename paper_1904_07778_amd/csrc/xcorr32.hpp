@@ -181,49 +181,88 @@ __device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v
   int32_t* accf = a.acc + (int64_t)f * nbl * 2;
   const int n = lane & 31;
   const int mb = 4 * (lane >> 5);
-  sfor<0, NU>([&](auto u) {
-    constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u], IM = plan.uIm[WC][u];
-    // the real and imaginary units of one tile pair, held by this wave one
-    // after the other: written together, one 8-byte (re, im) per baseline
-    constexpr bool PAIR = !IM && u + 1 < NU && plan.uI[WC][u + 1 < NU ? u + 1 : u] == I &&
-                          plan.uJ[WC][u + 1 < NU ? u + 1 : u] == J && plan.uIm[WC][u + 1 < NU ? u + 1 : u];
-    constexpr bool DONE = IM && u > 0 && plan.uI[WC][u > 0 ? u - 1 : 0] == I &&
-                          plan.uJ[WC][u > 0 ? u - 1 : 0] == J && !plan.uIm[WC][u > 0 ? u - 1 : 0];
-    if constexpr (!DONE) {
-      const int j = 32 * J + n;
-      const int32_t bias = (IM || PAIR) ? dcol[j] : 0;
-      sfor<0, 16>([&](auto v) {
-        const int i = 32 * I + 8 * (v / 4) + mb + (v % 4);
-        if ((N % 32 == 0 || i < N) && (J < I || j <= i)) {
-          int32_t* dst = accf + (i * (i + 1) / 2 + j) * 2;
-          int x;
-          asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(x) : "a"(acc[u][(int)v]));
-          if constexpr (PAIR) {
-            int y;
-            asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(y) : "a"(acc[u + 1][(int)v]));
-            const v2i re_im = v2i{x >> 8, (y - bias) >> 8};
-            v2i* d2 = reinterpret_cast<v2i*>(dst);
-            if constexpr (MODE == EPI_ATOMIC) {
-              atomicAdd(dst, re_im[0]);
-              atomicAdd(dst + 1, re_im[1]);
-            } else if constexpr (MODE == EPI_ADD) {
-              *d2 += re_im;
-            } else {
-              *d2 = re_im;
-            }
-          } else {
-            x = (x - bias) >> 8;
-            if constexpr (MODE == EPI_ATOMIC)
-              atomicAdd(dst + IM, x);
-            else if constexpr (MODE == EPI_ADD)
-              dst[IM] += x;
-            else
-              dst[IM] = x;
-          }
-        }
-      });
+  // calls body(u, v, pair, im, dst, bias) for every site (unit u, register
+  // v) this lane holds among units [U0, U1); bias: the diagonal value D_j
+  // for the imaginary part
+  auto sites = [&](auto U0, auto U1, auto body) {
+    sfor<decltype(U0)::value, decltype(U1)::value>([&](auto u) {
+      constexpr int I = plan.uI[WC][u], J = plan.uJ[WC][u], IM = plan.uIm[WC][u];
+      // the real and imaginary units of one tile pair, held by this wave one
+      // after the other: written together, one 8-byte (re, im) per baseline
+      constexpr bool PAIR = !IM && u + 1 < NU && plan.uI[WC][u + 1 < NU ? u + 1 : u] == I &&
+                            plan.uJ[WC][u + 1 < NU ? u + 1 : u] == J && plan.uIm[WC][u + 1 < NU ? u + 1 : u];
+      constexpr bool DONE = IM && u > 0 && plan.uI[WC][u > 0 ? u - 1 : 0] == I &&
+                            plan.uJ[WC][u > 0 ? u - 1 : 0] == J && !plan.uIm[WC][u > 0 ? u - 1 : 0];
+      if constexpr (!DONE) {
+        const int j = 32 * J + n;
+        const int32_t bias = (IM || PAIR) ? dcol[j] : 0;
+        sfor<0, 16>([&](auto v) {
+          const int i = 32 * I + 8 * (v / 4) + mb + (v % 4);
+          if ((N % 32 == 0 || i < N) && (J < I || j <= i))
+            body(u, v, std::integral_constant<bool, PAIR>{}, std::integral_constant<int, IM>{},
+                 accf + (i * (i + 1) / 2 + j) * 2, bias);
+        });
+      }
+    });
+  };
+  // this site's (re, im) or single value, with the imaginary bias removed
+  auto value = [&](auto u, auto v, auto pair, int32_t bias) {
+    int x;
+    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(x) : "a"(acc[u][(int)v]));
+    if constexpr (pair.value) {
+      constexpr int u1 = u + 1 < NU ? u + 1 : u;
+      int y;
+      asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(y) : "a"(acc[u1][(int)v]));
+      return v2i{x >> 8, (y - bias) >> 8};
+    } else {
+      return v2i{(x - bias) >> 8, 0};
     }
-  });
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using IN = std::integral_constant<int, NU>;
+  if constexpr (MODE == EPI_ADD) {
+    // Read-modify-write.  A wave's sites are distinct baselines, so the prior
+    // values of a chunk of units are all loaded before any of the chunk's
+    // sums is stored: one memory round trip per chunk instead of one per
+    // site (the compiler cannot prove the sites distinct and would otherwise
+    // wait for each load in turn).
+    constexpr int CH = 1;
+    sfor<0, (NU + CH - 1) / CH>([&](auto c) {
+      constexpr int u0 = decltype(c)::value * CH, u1 = u0 + CH < NU ? u0 + CH : NU;
+      using U0 = std::integral_constant<int, u0>;
+      using U1 = std::integral_constant<int, u1>;
+      v2i prev[CH][16];
+      sites(U0{}, U1{}, [&](auto u, auto v, auto pair, auto im, int32_t* dst, int) {
+        if constexpr (pair.value)
+          prev[u - u0][v] = *reinterpret_cast<const v2i*>(dst);
+        else
+          prev[u - u0][v][0] = dst[im.value];
+      });
+      sites(U0{}, U1{}, [&](auto u, auto v, auto pair, auto im, int32_t* dst, int32_t bias) {
+        const v2i r = value(u, v, pair, bias);
+        if constexpr (pair.value)
+          *reinterpret_cast<v2i*>(dst) = prev[u - u0][v] + r;
+        else
+          dst[im.value] = prev[u - u0][v][0] + r[0];
+      });
+    });
+  } else {
+    sites(I0{}, IN{}, [&](auto u, auto v, auto pair, auto im, int32_t* dst, int32_t bias) {
+      const v2i r = value(u, v, pair, bias);
+      if constexpr (pair.value) {
+        if constexpr (MODE == EPI_ATOMIC) {
+          atomicAdd(dst, r[0]);
+          atomicAdd(dst + 1, r[1]);
+        } else {
+          *reinterpret_cast<v2i*>(dst) = r;
+        }
+      } else if constexpr (MODE == EPI_ATOMIC) {
+        atomicAdd(dst + im.value, r[0]);
+      } else {
+        dst[im.value] = r[0];
+      }
+    });
+  }
 }
 
 // One work item: channel group `group` (channels CPW*group ..) over time
