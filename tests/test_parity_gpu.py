@@ -106,6 +106,37 @@ def test_multi_call_integration_and_keep():
         assert np.array_equal(out[0].numpy(), oracle.correlate(blocks[0]))
 
 
+@pytest.mark.parametrize("N", [192, 256, 96, 70])
+def test_accumulating_calls_every_kernel(N):
+    """Read-modify-write epilogues: calls of under 512 samples keep one
+    workgroup per channel (no time split), so the second and later calls of
+    an integration add to the accumulator in place.  N = 192 and 96 run the
+    16-row kernel, N = 256 the 32-row kernel, N = 70 the staging kernel;
+    extreme codes in some blocks push the sums to large magnitudes of both
+    signs.  Every channel against the oracle after each call."""
+    import torch
+    from paper_1904_07778_amd.xeng import Plan
+    F = 3
+    rng = np.random.default_rng(N + 5)
+    lens = [300, 500, 64, 511, 200]
+    blocks = []
+    for k, t in enumerate(lens):
+        re, im = rng.integers(-8, 8, size=(t, F, N)), rng.integers(-8, 8, size=(t, F, N))
+        if k in (1, 3):
+            re[:, :, ::2], im[:, :, 1::3] = -8, 7
+        blocks.append(synth.pack(re, im))
+    print(f"accumulating calls N={N}", flush=True)
+    e = oracle.Engine(N, F)
+    with Plan([(N, F, 512)]) as p:
+        for k, b in enumerate(blocks):
+            p.correlate([torch.from_numpy(b).cuda()])
+            e.correlate(b)
+            out, n = p.dump(keep=True, to_host=True)
+            want, _ = e.dump(keep=True)
+            assert n == [sum(lens[:k + 1])]
+            assert np.array_equal(out[0].numpy(), want), (k, first_mismatch(out[0].numpy(), want))
+
+
 def test_dump_to_device_buffer():
     import torch
     from paper_1904_07778_amd.xeng import Plan
