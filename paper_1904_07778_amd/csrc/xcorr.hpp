@@ -206,6 +206,17 @@ __device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v
       const int i = 16 * I + m0 + vv;
       if (i >= a.N) continue;
       int32_t* rowp = accf + (i * (i + 1) / 2) * 2;
+      // read-modify-write: the row's prior values first (distinct baselines),
+      // then the sums, one memory round trip per row segment
+      v2i prev[NT];
+      if (MODE == EPI_ADD) {
+#pragma unroll
+        for (int J = J0; J <= J1; ++J) {
+          const int j = 16 * J + n;
+          if (J == I && j > i) continue;
+          prev[J - J0] = *reinterpret_cast<const v2i*>(rowp + 2 * j);
+        }
+      }
 #pragma unroll
       for (int J = J0; J <= J1; ++J) {
         const int j = 16 * J + n;
@@ -218,8 +229,7 @@ __device__ __forceinline__ void epilogue(const Args& a, int f, int lane, const v
           atomicAdd(dst, re);
           atomicAdd(dst + 1, im);
         } else if (MODE == EPI_ADD) {
-          const v2i old = *reinterpret_cast<const v2i*>(dst);
-          *reinterpret_cast<v2i*>(dst) = v2i{old[0] + re, old[1] + im};
+          *reinterpret_cast<v2i*>(dst) = prev[J - J0] + v2i{re, im};
         } else {
           *reinterpret_cast<v2i*>(dst) = v2i{re, im};
         }
