@@ -33,18 +33,20 @@ inline const KernelInfo* x32_kernel(int n) {
   return k;
 }
 // 16-row-tile ring kernel on v_mfma_i32_16x16x64_i8, N a multiple of 16 up
-// to 240 (several translation units; x16_kernel asks each).
+// to 256 (several translation units; x16_kernel asks each).
 const KernelInfo* x16_kernel_a(int n);
 const KernelInfo* x16_kernel_b(int n);
 const KernelInfo* x16_kernel_c(int n);
 const KernelInfo* x16_kernel_d(int n);
 const KernelInfo* x16_kernel_e(int n);
+const KernelInfo* x16_kernel_f(int n);
 inline const KernelInfo* x16_kernel(int n) {
   const KernelInfo* k = x16_kernel_a(n);
   if (!k) k = x16_kernel_b(n);
   if (!k) k = x16_kernel_c(n);
   if (!k) k = x16_kernel_d(n);
   if (!k) k = x16_kernel_e(n);
+  if (!k) k = x16_kernel_f(n);
   return k;
 }
 

@@ -1,5 +1,5 @@
 // xcorr16.hpp - gfx950 X-engine kernel on 16-row tiles (v_mfma_i32_16x16x64_i8),
-// N a multiple of 16 up to 240.
+// N a multiple of 16 up to 256.
 //
 // Result (paper Sec. 2 and Sec. 2.2): for each channel f of the grid and each
 // pair 0 <= j <= i < N, the exact int32 sum over the launch's time range of
@@ -77,7 +77,11 @@ constexpr int units(int nt) { return nt * (nt + 1); }
 constexpr int waves_per_channel(int nt) {
   return units(nt) <= MAX_UNITS_PER_WAVE ? 1 : units(nt) <= 2 * MAX_UNITS_PER_WAVE ? 2 : 4;
 }
-constexpr bool supported(int n) { return n % 16 == 0 && n >= 16 && units(tiles(n)) <= 4 * MAX_UNITS_PER_WAVE; }
+// With four waves per channel a wave may hold up to 68 units (N = 256: 272
+// accumulator registers, the 256 AGPRs and 16 VGPRs of its 512 at one wave
+// per SIMD); the choice of 1, 2 or 4 waves per channel keeps the 60 limit.
+constexpr int MAX_UNITS_PER_WAVE_4 = 68;
+constexpr bool supported(int n) { return n % 16 == 0 && n >= 16 && units(tiles(n)) <= 4 * MAX_UNITS_PER_WAVE_4; }
 
 template <int NT, int W>
 struct Plan16 {
@@ -155,7 +159,7 @@ struct Shape {
   static constexpr int LPW_MIN = LOADS / WAVES;
   static constexpr int DIAG_BYTES = CPW * N * 4;
   static constexpr int LDS_BYTES = S * STAGE_BYTES > DIAG_BYTES ? S * STAGE_BYTES : DIAG_BYTES;
-  static_assert(supported(N), "N must be a multiple of 16 up to 240");
+  static_assert(supported(N), "N must be a multiple of 16 up to 256");
   static_assert(LOADS * 1024 == STAGE_BYTES, "a stage is whole 1 KB loads");
   static_assert(S >= 3 && (S - 2) * (CPW == 1 ? (LOADS + 1) / 2 : LPW_MAX) < 64, "ring depth");
   static_assert(KPS >= 2 && KPS % 2 == 0, "an even number of steps per stage");

@@ -27,3 +27,34 @@ def run_engine(blocks, N, F, max_t=None, keep_dumps=()):
 def first_mismatch(got, want):
     bad = np.argwhere(got != want)
     return f"{len(bad)} mismatches, first at {tuple(bad[0])}: got {got[tuple(bad[0])]} want {want[tuple(bad[0])]}" if len(bad) else ""
+
+
+KIND_X16, KIND_X32, KIND_STAGE = 0, 1, 2
+
+
+class forced_kernel:
+    """Context: plain plans of (N, F, max_time_per_call) made inside it use the
+    given tile shape (a one-line tuning cache; the cache is cleared on exit)."""
+
+    def __init__(self, N, F, max_t, kind, split=2):
+        self.line = (N, F, max_t, kind, split)
+
+    def __enter__(self):
+        import os
+        import tempfile
+        import torch
+        from paper_1904_07778_amd import xeng as X
+        N, F, max_t, kind, split = self.line
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        bucket = lambda v: max(0, int(v - 1).bit_length())   # ceil(log2 v), the cache's buckets
+        fd, path = tempfile.mkstemp(suffix=".txt")
+        with os.fdopen(fd, "w") as fh:
+            fh.write(f"{arch} 0 {N} {bucket(F)} {bucket(max_t)} {kind} {split} 0\n")
+        X.xeng_tune_cache_clear()
+        X.xeng_tune_cache_load(path)
+        os.unlink(path)
+        return self
+
+    def __exit__(self, *exc):
+        from paper_1904_07778_amd import xeng as X
+        X.xeng_tune_cache_clear()

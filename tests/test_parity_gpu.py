@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import first_mismatch, gpu_available, run_engine
+from tests.gpu_util import KIND_STAGE, KIND_X32, first_mismatch, forced_kernel, gpu_available, run_engine
 
 pytestmark = pytest.mark.gpu
 if not gpu_available():
@@ -106,14 +106,18 @@ def test_multi_call_integration_and_keep():
         assert np.array_equal(out[0].numpy(), oracle.correlate(blocks[0]))
 
 
-@pytest.mark.parametrize("N", [192, 256, 96, 70])
-def test_accumulating_calls_every_kernel(N):
+@pytest.mark.parametrize("N,kind", [(192, None), (256, None), (96, None), (70, None), (256, KIND_X32),
+                                    (96, KIND_X32), (64, KIND_STAGE)], ids=lambda x: str(x))
+def test_accumulating_calls_every_kernel(N, kind):
     """Read-modify-write epilogues: calls of under 512 samples keep one
     workgroup per channel (no time split), so the second and later calls of
-    an integration add to the accumulator in place.  N = 192 and 96 run the
-    16-row kernel, N = 256 the 32-row kernel, N = 70 the staging kernel;
-    extreme codes in some blocks push the sums to large magnitudes of both
-    signs.  Every channel against the oracle after each call."""
+    an integration add to the accumulator in place.  By default N = 192,
+    256 and 96 run the 16-row kernel and N = 70 the staging kernel; the
+    32-row kernel (N = 256, 96) and the staging kernel at a multiple of 16
+    are forced through the tuning cache.  Extreme codes in some blocks push
+    the sums to large magnitudes of both signs.  Every channel against the
+    oracle after each call."""
+    import contextlib
     import torch
     from paper_1904_07778_amd.xeng import Plan
     F = 3
@@ -125,9 +129,10 @@ def test_accumulating_calls_every_kernel(N):
         if k in (1, 3):
             re[:, :, ::2], im[:, :, 1::3] = -8, 7
         blocks.append(synth.pack(re, im))
-    print(f"accumulating calls N={N}", flush=True)
+    print(f"accumulating calls N={N} kind={kind}", flush=True)
     e = oracle.Engine(N, F)
-    with Plan([(N, F, 512)]) as p:
+    force = forced_kernel(N, F, 512, kind) if kind is not None else contextlib.nullcontext()
+    with force, Plan([(N, F, 512)]) as p:
         for k, b in enumerate(blocks):
             p.correlate([torch.from_numpy(b).cuda()])
             e.correlate(b)
@@ -287,23 +292,28 @@ def _closed_form(re, im, T):
     return vis
 
 
-@pytest.mark.parametrize("batched", [False, True], ids=["plain", "batched"])
-@pytest.mark.parametrize("N", [16, 192, 256])
-def test_ring_kernel_at_int32_bound(N, batched):
+@pytest.mark.parametrize("N,batched,kind", [(16, False, None), (16, True, None), (192, False, None),
+                                             (192, True, None), (256, False, None), (256, True, None),
+                                             (256, False, KIND_X32), (192, False, KIND_X32)],
+                         ids=lambda x: str(x))
+def test_ring_kernel_at_int32_bound(N, batched, kind):
     """Ring kernels at the library's integration limit: all codes -8,
     T = 16,777,215 in one call, so every workgroup integrates the largest
     time chunk its kernel takes (the x256-scaled sums at their headroom) and
-    the chunks meet in the accumulator by atomic adds.  N = 16 and 192 run
-    the 16-row-tile kernel (in a batched plan, inside the persistent launch);
-    N = 256 the 32-row-tile kernel (in a batched plan, as a launch of its
-    own).  Every visibility must be 128 T = 2,147,483,520 (the closed form),
+    the chunks meet in the accumulator by atomic adds.  By default every N
+    here runs the 16-row-tile kernel (in a batched plan N = 16 and 192 run
+    inside the persistent launch, N = 256 as a launch of its own); the
+    32-row-tile kernel is forced through the tuning cache for N = 256 and
+    192.  Every visibility must be 128 T = 2,147,483,520 (the closed form),
     exact."""
+    import contextlib
     import torch
     from paper_1904_07778_amd.xeng import XENG_MAX_INTEGRATION, Plan
     T, F = XENG_MAX_INTEGRATION, 1
-    print(f"ring kernel int32 bound N={N} batched={batched}", flush=True)
+    print(f"ring kernel int32 bound N={N} batched={batched} kind={kind}", flush=True)
     v = torch.full((T, F, N), 0x88, dtype=torch.uint8, device="cuda")
-    with Plan([(N, F, T)], batch=batched) as p:
+    force = forced_kernel(N, F, T, kind) if kind is not None else contextlib.nullcontext()
+    with force, Plan([(N, F, T)], batch=batched) as p:
         p.correlate([v])
         out, n = p.dump(to_host=True)
     del v
