@@ -42,7 +42,7 @@ struct ArrayState {
                        // the next launch overwrites it with plain stores, or
                        // zeroes it first when it must add atomically)
   const KernelInfo* k = nullptr;  // kernel of the plain launch
-  int split = 2;                  // plain launch: aim for split * n_cu workgroups
+  int split = 1;                  // plain launch: aim for split * n_cu workgroups
   bool own_launch = false;        // batched plan: a plain launch of its own inside the
                                   // graph instead of items of the persistent launch
 };
@@ -204,10 +204,18 @@ void record_choice(const xeng_plan_t* p, const ArrayState& s, int64_t T) {
   g_tune[key] = TuneVal{kind_of(s.k, s.d.n_inputs), s.split, s.own_launch ? 1 : 0};
 }
 
+// Untuned time split: two workgroups per CU where the kernel's LDS lets
+// several share a CU (the staging kernel, the ring kernel at N = 16), one
+// where its ring fills most of the CU's LDS: a second workgroup could not
+// run beside the first, and aiming for it only splits time into atomic adds
+// and a zeroing pass (45-60% slower at N = 48..112, F = 1024).
+int default_split(const KernelInfo* k) { return k->lds_bytes <= 64 * 1024 ? 2 : 1; }
+
 int init_slot(xeng_plan_t* p, ArrayState& s, const xeng_array_desc& d) {
   s = ArrayState{};
   s.d = d;
   s.k = default_kernel(d);
+  s.split = default_split(s.k);
   apply_cached(p, s, d.max_time_per_call);
   s.acc_bytes = (size_t)d.n_chans * nbl_of(d.n_inputs) * 2 * sizeof(int32_t);
   hipError_t e = hipMalloc(&s.acc, s.acc_bytes);
