@@ -74,8 +74,12 @@ __device__ __forceinline__ void sfor(F&& f) {
 
 constexpr int tiles(int n) { return n / 16; }
 constexpr int units(int nt) { return nt * (nt + 1); }
+// Waves per channel: 1 up to 60 units, else 2 up to 120, else 4; N = 128 (72
+// units) takes 4 waves of 18, one channel per workgroup (0.259 against 0.285
+// ms at F = 1024, T = 8192 with two waves of 36; N = 144 and 160 measured
+// the same either way).
 constexpr int waves_per_channel(int nt) {
-  return units(nt) <= MAX_UNITS_PER_WAVE ? 1 : units(nt) <= 2 * MAX_UNITS_PER_WAVE ? 2 : 4;
+  return units(nt) <= MAX_UNITS_PER_WAVE ? 1 : nt == 8 ? 4 : units(nt) <= 2 * MAX_UNITS_PER_WAVE ? 2 : 4;
 }
 // With four waves per channel a wave may hold up to 68 units (N = 256: 272
 // accumulator registers, the 256 AGPRs and 16 VGPRs of its 512 at one wave
